@@ -1,0 +1,482 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks the oracle against a value the paper prints, a closed form,
+an invariant, a library routine, or a brute-force evaluation by a different
+route (full 8-component dual-quaternion algebra in 50-digit mpmath), chosen so
+that a dropped term, a wrong sign or index, or a transposed operand in the
+oracle fails at least one of them.  No GPU is used.
+"""
+import json
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy import ndimage, stats
+
+import oracle as O
+from paper_2103_07414_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers --
+# Full (8-component) dual quaternions, written from the textbook definitions:
+# quaternion (w, x, y, z) with the Hamilton product; unit DQ of a rigid motion
+# = r + eps * (1/2) t r; point transform by the sandwich q (1 + eps p) q^+,
+# where q^+ conjugates both the quaternion and the dual unit.
+
+def qmul(a, b):
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return (aw * bw - ax * bx - ay * by - az * bz,
+            aw * bx + ax * bw + ay * bz - az * by,
+            aw * by - ax * bz + ay * bw + az * bx,
+            aw * bz + ax * by - ay * bx + az * bw)
+
+
+def qconj(a):
+    return (a[0], -a[1], -a[2], -a[3])
+
+
+def dq_full(theta, tx, ty):
+    r = (mp.cos(theta / 2), mp.mpf(0), mp.mpf(0), mp.sin(theta / 2))
+    d = tuple(mp.mpf("0.5") * c for c in qmul((0, tx, ty, 0), r))
+    return r, d
+
+
+def dq_transform(r, d, px, py):
+    """Sandwich product of a unit DQ with the point (px, py, 0)."""
+    # (r + eps d)(1 + eps p)(r* - eps d*)  ->  real part r r*, dual part
+    # r p r* + d r* - r d*
+    p = (0, px, py, 0)
+    rc, dc = qconj(r), qconj(d)
+    real = qmul(r, rc)
+    dual = tuple(a + b - c for a, b, c in zip(qmul(qmul(r, p), rc), qmul(d, rc), qmul(r, dc)))
+    assert abs(real[0] - 1) < mp.mpf(10) ** -40
+    return dual[1], dual[2], dual[3]
+
+
+def blend_full(x, scale, thetas, ts, wts, alpha, zx, zy):
+    """Eqs. (2)-(4) on full DQs, DLB normalisation, then Eq. (1)."""
+    W = mp.mpf(0)
+    sb = mp.mpf(0)
+    rb = [mp.mpf(0)] * 4
+    db = [mp.mpf(0)] * 4
+    for j in range(len(scale)):
+        dx = mp.mpf(zx) - mp.mpf(x[j][0])
+        dy = mp.mpf(zy) - mp.mpf(x[j][1])
+        w = mp.exp(-mp.mpf(alpha) * (dx * dx + dy * dy)) * wts[j]
+        r, d = dq_full(mp.mpf(thetas[j]), mp.mpf(ts[j][0]), mp.mpf(ts[j][1]))
+        W += w
+        sb += w * mp.mpf(scale[j])
+        rb = [a + w * b for a, b in zip(rb, r)]
+        db = [a + w * b for a, b in zip(db, d)]
+    sb /= W
+    rb = [a / W for a in rb]
+    db = [a / W for a in db]
+    nr = mp.sqrt(sum(a * a for a in rb))
+    rb = tuple(a / nr for a in rb)
+    db = tuple(a / nr for a in db)
+    px, py, pz = dq_transform(rb, db, mp.mpf(zx), mp.mpf(zy))
+    assert abs(pz) < mp.mpf(10) ** -30
+    return float(sb * px), float(sb * py)
+
+
+def rot(theta):
+    return np.array([[np.cos(theta), -np.sin(theta)], [np.sin(theta), np.cos(theta)]])
+
+
+# ------------------------------------------------------- paper parameters --
+
+def test_alpha_scaling_matches_paper_parameters():
+    g = json.load(open(os.path.join(GOLDEN, "paper_parameters.json")))
+    a0 = g["alpha"]["value"]
+    rw, rh = g["reference_resolution"]["value"]
+    # at the reference resolution s = 1, so alpha is the printed value
+    assert O.alpha(rw, rh) == a0
+    # doubling both sides gives s = 2 and alpha / 4
+    assert O.alpha(2 * rw, 2 * rh) == pytest.approx(a0 / 4, rel=1e-15)
+    # 1280 x 1024: s = (1280/480 + 1024/270) / 2
+    s = (1280 / 480 + 1024 / 270) / 2
+    assert O.alpha(1280, 1024) == pytest.approx(a0 / s ** 2, rel=1e-15)
+
+
+# -------------------------------------------------------- dual quaternions --
+
+@pytest.mark.parametrize("theta,tx,ty", [(0.0, 0.0, 0.0), (0.3, 5.0, -2.0),
+                                         (-2.9, 117.25, 40.5), (3.1, -0.5, 800.0)])
+def test_planar_dq_equals_full_dq(theta, tx, ty):
+    """Footnote to Eq. (1): the 4 kept components are (r_w, r_z, d_x, d_y) of
+    the full DQ and the other 4 are zero."""
+    mp.mp.dps = 50
+    r, d = dq_full(mp.mpf(theta), mp.mpf(tx), mp.mpf(ty))
+    q = O.dq_from_rt(theta, tx, ty)
+    assert np.allclose(q, [float(r[0]), float(r[3]), float(d[1]), float(d[2])],
+                       rtol=0, atol=1e-13)
+    for zero in (r[1], r[2], d[0], d[3]):
+        assert abs(zero) < 1e-40
+
+
+@pytest.mark.parametrize("theta,tx,ty,s,px,py", [
+    (0.3, 5.0, -2.0, 1.0, 10.0, 20.0), (-1.2, -40.0, 3.5, 0.93, 300.0, -7.0),
+    (2.5, 0.0, 0.0, 1.07, 1.0, 1.0)])
+def test_warp_point_equals_sandwich_product(theta, tx, ty, s, px, py):
+    """Eq. (1): s q(x) = s (R x + t); the DQ transform is the sandwich product."""
+    mp.mp.dps = 50
+    r, d = dq_full(mp.mpf(theta), mp.mpf(tx), mp.mpf(ty))
+    bx, by, _ = dq_transform(r, d, mp.mpf(px), mp.mpf(py))
+    ox, oy = O.warp_point(s, O.dq_from_rt(theta, tx, ty), px, py)
+    assert ox == pytest.approx(s * float(bx), abs=1e-11)
+    assert oy == pytest.approx(s * float(by), abs=1e-11)
+    # and the matrix form with an independently built rotation
+    want = s * (rot(theta) @ np.array([px, py]) + np.array([tx, ty]))
+    assert np.allclose([ox, oy], want, atol=1e-11)
+
+
+def test_dq_decode_is_scale_invariant():
+    """Normalising by the real-part norm makes the decode independent of a
+    positive common factor (Eq. (3) then normalisation)."""
+    q = O.dq_from_rt(0.7, 12.0, -3.0)
+    a = O.dq_decode(q)
+    b = O.dq_decode(3.7 * q)
+    assert np.allclose(a, b, atol=1e-13)
+    assert np.allclose(a, (np.cos(0.7), np.sin(0.7), 12.0, -3.0), atol=1e-13)
+
+
+# ------------------------------------------------------ weighted fit -------
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_weighted_fit_recovers_exact_similarity(seed):
+    """Eqs. (18)-(20): noise-free similarity data -> the similarity exactly,
+    for any positive weights."""
+    rng = np.random.default_rng(seed)
+    n = 9
+    x = rng.uniform(-200, 600, (n, 2))
+    theta = rng.uniform(-3.0, 3.0)
+    s = rng.uniform(0.5, 2.0)
+    t = rng.uniform(-100, 100, 2)
+    y = s * (x @ rot(theta).T + t)          # y = s (R x + t), Eq. (1)
+    w = rng.uniform(0.05, 1.0, n)
+    sf, q, degenerate = O.weighted_fit(x, y, w)
+    assert not degenerate
+    ct, st, tx, ty = O.dq_decode(q)
+    assert sf == pytest.approx(s, rel=1e-12)
+    assert np.arctan2(st, ct) == pytest.approx(theta, abs=1e-12)
+    assert np.allclose([tx, ty], t, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [5, 6, 7, 8, 9])
+def test_weighted_fit_rotation_matches_svd_procrustes(seed):
+    """Eq. (18) on noisy weighted data: the rotation equals U diag(1, det) V^T
+    from numpy's SVD, and minimises the weighted misfit over all angles."""
+    rng = np.random.default_rng(seed)
+    n = 12
+    x = rng.uniform(0, 500, (n, 2))
+    y = x @ rot(rng.uniform(-2, 2)).T * rng.uniform(0.8, 1.2) + rng.normal(0, 30, (n, 2))
+    if seed == 9:
+        y[:, 0] = -y[:, 0]                  # a reflection: det correction matters
+    w = rng.uniform(0.0, 1.0, n)
+    sf, q, _ = O.weighted_fit(x, y, w)
+    ct, st, _, _ = O.dq_decode(q)
+    xm = (w[:, None] * x).sum(0) / w.sum()
+    ym = (w[:, None] * y).sum(0) / w.sum()
+    M = ((y - ym) * w[:, None]).T @ (x - xm)
+    U, _, Vt = np.linalg.svd(M)
+    R = U @ np.diag([1.0, np.linalg.det(U @ Vt)]) @ Vt
+    assert np.allclose([[ct, -st], [st, ct]], R, atol=1e-10)
+    # brute-force scan over the angle of the weighted rotational misfit
+    ang = np.linspace(-np.pi, np.pi, 200001)
+    a = (x - xm)
+    b = (y - ym)
+    score = (w * (b[:, 0] * a[:, 0] + b[:, 1] * a[:, 1])).sum() * np.cos(ang) \
+        + (w * (b[:, 1] * a[:, 0] - b[:, 0] * a[:, 1])).sum() * np.sin(ang)
+    assert np.arctan2(st, ct) == pytest.approx(ang[np.argmax(score)], abs=1e-4)
+
+
+def test_weighted_fit_scale_and_translation_invariances():
+    """Scaling the targets scales s; shifting the targets by d shifts the
+    translation by d/s; rotating the targets adds to the angle."""
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0, 300, (10, 2))
+    y = x + rng.normal(0, 5, (10, 2))
+    w = rng.uniform(0.1, 1, 10)
+    s0, q0, _ = O.weighted_fit(x, y, w)
+    s1, q1, _ = O.weighted_fit(x, 2.5 * y, w)
+    assert s1 == pytest.approx(2.5 * s0, rel=1e-12)
+    d = np.array([7.0, -3.0])
+    s2, q2, _ = O.weighted_fit(x, y + d, w)
+    c0, n0, tx0, ty0 = O.dq_decode(q0)
+    _, _, tx2, ty2 = O.dq_decode(q2)
+    assert s2 == pytest.approx(s0, rel=1e-12)
+    assert np.allclose([tx2 - tx0, ty2 - ty0], d / s0, atol=1e-9)
+    s3, q3, _ = O.weighted_fit(x, y @ rot(0.4).T, w)
+    c3, n3, _, _ = O.dq_decode(q3)
+    assert np.arctan2(n3, c3) == pytest.approx(np.arctan2(n0, c0) + 0.4, abs=1e-12)
+
+
+def test_weighted_fit_degenerate_sources():
+    """All weighted sources coincide -> translation between the centroids."""
+    x = np.tile([[10.0, 20.0]], (5, 1))
+    y = np.array([[11, 19], [12, 22], [13, 21], [9, 20], [10, 18]], dtype=float)
+    w = np.array([1.0, 0.5, 0.25, 1.0, 0.0])
+    s, q, degenerate = O.weighted_fit(x, y, w)
+    assert degenerate and s == 1.0
+    ct, st, tx, ty = O.dq_decode(q)
+    ym = (w[:, None] * y).sum(0) / w.sum()
+    assert (ct, st) == (1.0, 0.0)
+    assert np.allclose([tx, ty], ym - x[0], atol=1e-12)
+
+
+def test_mstep_exact_similarity_every_row():
+    """M-step with p = 1 on one exact similarity: every match recovers it."""
+    src, dst = synth.similarity_matches(60, 320, 240, 0.05, 1.03, (4.0, -6.0), seed=3)
+    x = src.astype(np.float64)
+    c = np.array([159.5, 119.5])
+    y = c + 1.03 * (x - c) @ rot(0.05).T + np.array([4.0, -6.0])   # exact in FP64
+    s, q = O.mstep(x, y, np.ones(60), O.alpha(320, 240))
+    for i in range(60):
+        ox, oy = O.warp_point(s[i], q[i], 37.0, 211.0)
+        want = c + 1.03 * rot(0.05) @ (np.array([37.0, 211.0]) - c) + [4.0, -6.0]
+        assert np.allclose([ox, oy], want, atol=1e-9)
+    assert np.allclose(s, 1.03, rtol=1e-12)
+
+
+def test_mstep_weights_follow_eq4():
+    """The M-step weight of match j at match i is exp(-alpha d^2) p_j: with
+    p_j = 0 except two matches, the fit is the exact two-point similarity."""
+    x = np.array([[0.0, 0.0], [100.0, 0.0], [50.0, 80.0], [400.0, 300.0]])
+    y = np.array([[5.0, 5.0], [5.0, 105.0], [9.0, 9.0], [0.0, 0.0]])
+    p = np.array([1.0, 1.0, 0.0, 0.0])
+    s, q = O.mstep(x, y, p, 1e-4)
+    # two points: (0,0)->(5,5), (100,0)->(5,105): rotation +90 deg, scale 1
+    for i in range(4):
+        ct, st, tx, ty = O.dq_decode(q[i])
+        assert np.arctan2(st, ct) == pytest.approx(np.pi / 2, abs=1e-12)
+        assert s[i] == pytest.approx(1.0, rel=1e-12)
+        assert np.allclose([tx, ty], [5.0, 5.0], atol=1e-10)
+
+
+# ------------------------------------------------------ blend / field -------
+
+def _random_fits(rng, n):
+    x = rng.uniform(0, 40, (n, 2))
+    thetas = rng.uniform(-0.4, 0.4, n)
+    ts = rng.uniform(-6, 6, (n, 2))
+    scale = rng.uniform(0.9, 1.1, n)
+    q = np.array([O.dq_from_rt(a, b[0], b[1]) for a, b in zip(thetas, ts)])
+    return x, thetas, ts, scale, q
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_field_equals_full_dq_brute_force(seed):
+    """Eqs. (2)-(4) + normalisation + Eq. (1), N <= 8 on a 6 x 5 grid, against
+    50-digit full-DQ blending: within 1e-9 px."""
+    mp.mp.dps = 50
+    rng = np.random.default_rng(seed)
+    n = 8
+    x, thetas, ts, scale, q = _random_fits(rng, n)
+    mask = np.ones(n, dtype=np.uint8)
+    mask[3] = 0
+    alpha = 2e-3
+    rc, F = O.field(x, scale, q, mask, alpha, 10, 12, 6, 5)
+    assert rc == 0
+    for k in range(5):
+        for i in range(6):
+            want = blend_full(x, scale, thetas, ts, mask.astype(float), alpha, 10 + i, 12 + k)
+            assert np.allclose(F[k, i], want, atol=1e-9), (k, i)
+
+
+def test_field_identity_matches_give_identity():
+    rng = np.random.default_rng(4)
+    src = rng.uniform(0, 319, (200, 2)).astype(np.float32)
+    f = O.fit(src, src, 320, 240)
+    assert f.status == 0 and f.n_in == 200
+    rc, F = O.field(src, f.scale, f.q, f.mask, f.alpha, 0, 0, 40, 30)
+    gy, gx = np.mgrid[0:30, 0:40]
+    assert np.abs(F - np.stack([gx, gy], -1)).max() < 1e-9
+
+
+def test_field_single_similarity_reproduced_everywhere():
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 319, (200, 2))
+    th, s, t = -0.07, 0.96, np.array([3.0, 8.0])
+    y = s * (x @ rot(th).T + t)
+    f = O.fit(x, y, 320, 240)
+    assert f.status == 0 and f.n_in == 200
+    rc, F = O.field(x, f.scale, f.q, f.mask, f.alpha, -20, -10, 360, 260)
+    gy, gx = np.mgrid[-10:250, -20:340]
+    want = s * (np.stack([gx, gy], -1) @ rot(th).T + t)
+    assert np.abs(F - want).max() < 1e-9
+
+
+def test_field_points_equal_grid():
+    rng = np.random.default_rng(6)
+    x, _, _, scale, q = _random_fits(rng, 7)
+    mask = np.ones(7, dtype=np.uint8)
+    rc, F = O.field(x, scale, q, mask, 1e-3, 3, 4, 5, 6)
+    pts = np.array([[3 + i, 4 + k] for k in range(6) for i in range(5)], dtype=float)
+    rc2, P = O.field_points(x, scale, q, mask, 1e-3, pts)
+    assert np.array_equal(P, F.reshape(-1, 2))
+
+
+def test_field_no_inliers():
+    x = np.zeros((3, 2))
+    q = np.array([O.dq_from_rt(0, 0, 0)] * 3)
+    rc, F = O.field(x, np.ones(3), q, np.zeros(3, np.uint8), 1e-3, 0, 0, 2, 2)
+    assert rc == O.ENOINLIERS and np.isnan(F).all()
+
+
+# ------------------------------------------------------------ posterior -----
+
+def test_posterior_matches_library_gaussian():
+    """2D isotropic Gaussian density from scipy + Bayes rule with a uniform
+    outlier density u."""
+    rng = np.random.default_rng(7)
+    n = 50
+    e = rng.normal(0, 2.0, (n, 2))
+    e[:10] = rng.uniform(-200, 200, (10, 2))
+    e2 = (e ** 2).sum(1)
+    p = rng.uniform(0.2, 1.0, n)
+    u = 1.0 / (320 * 240)
+    pn, s2, g = O.posterior(e2, p, u)
+    assert s2 == pytest.approx((p * e2).sum() / (2 * p.sum()), rel=1e-13)
+    assert g == pytest.approx(p.mean(), rel=1e-13)
+    L = stats.multivariate_normal(mean=[0, 0], cov=s2 * np.eye(2)).pdf(e)
+    want = g * L / (g * L + (1 - g) * u)
+    assert np.allclose(pn, want, rtol=1e-10, atol=1e-300)
+
+
+def test_posterior_ml_variance_and_clamps():
+    """p = 1: sigma^2 is the ML per-axis variance of zero-mean residuals;
+    floors and clamps apply."""
+    rng = np.random.default_rng(8)
+    e = rng.normal(0, 3.0, (400, 2))
+    pn, s2, g = O.posterior((e ** 2).sum(1), np.ones(400), 1e-5)
+    assert s2 == pytest.approx(np.mean(e ** 2), rel=1e-12)
+    assert g == 0.95                                   # clamped from 1
+    pn, s2, g = O.posterior(np.zeros(10), np.full(10, 0.01), 1e-5)
+    assert s2 == 1e-2 and g == 0.05                    # floors
+
+
+# ------------------------------------------------------------------ EM ------
+
+def test_em_planted_far_outliers_recovered_exactly():
+    rng = np.random.default_rng(9)
+    n = 150
+    x = rng.uniform(0, 319, (n, 2))
+    y = 1.02 * (x @ rot(0.03).T + [2.0, -1.0])
+    out = rng.choice(n, 20, replace=False)
+    y[out] += rng.uniform(200, 300, (20, 2)) * rng.choice([-1, 1], (20, 2))
+    f = O.fit(x, y, 320, 240)
+    truth = np.ones(n, bool)
+    truth[out] = False
+    assert f.status == 0
+    assert np.array_equal(f.mask.astype(bool), truth)
+    assert 2 <= f.iters <= 10
+    assert f.sigma2 == pytest.approx(1e-2)
+
+
+@pytest.mark.parametrize("pair", [1, 2, 3])
+def test_em_config1_recovers_truth_labels(pair):
+    P = synth.gen_config(1, pair, with_frame=False)
+    f = O.fit(P.src, P.dst, 320, 240)
+    assert f.status == 0
+    assert np.array_equal(f.mask.astype(bool), P.inlier)
+
+
+def test_em_identity_converges_in_two():
+    rng = np.random.default_rng(10)
+    x = rng.uniform(0, 300, (50, 2))
+    f = O.fit(x, x, 320, 240)
+    assert f.status == 0 and f.iters == 2 and f.n_in == 50
+    assert np.allclose(f.p, 1.0)
+
+
+def test_em_max_iter_warning_and_errors():
+    P = synth.gen_config(2, 3, with_frame=False)
+    f = O.fit(P.src, P.dst, 1280, 1024, O.params(max_iter=3))
+    assert f.status == O.WARN_NOT_CONVERGED and f.iters == 3
+    x = np.zeros((1, 2))
+    assert O.fit(x, x, 10, 10).status == O.ETOOFEW
+    x = np.zeros((4, 2))
+    y = x.copy()
+    y[2, 1] = np.nan
+    assert O.fit(x, y, 10, 10).status == O.ENONFINITE
+    assert O.fit(x, x, 0, 10).status == O.EINVAL
+
+
+def test_em_final_p_is_posterior_of_final_residuals_consistent():
+    """After the fit, mask == (p rounded to FP32 > 0.5)."""
+    P = synth.gen_config(1, 2, with_frame=False)
+    f = O.fit(P.src, P.dst, 320, 240)
+    assert np.array_equal(f.mask.astype(bool), f.p.astype(np.float32) > np.float32(0.5))
+
+
+# --------------------------------------------------------- bilinear / warp --
+
+def test_bilinear_matches_scipy():
+    rng = np.random.default_rng(12)
+    img = rng.integers(0, 256, (7, 9, 3), dtype=np.uint8)
+    for _ in range(200):
+        ux, uy = rng.uniform(0, 8), rng.uniform(0, 6)
+        got = O.bilinear(img, ux, uy)
+        for c in range(3):
+            want = ndimage.map_coordinates(img[..., c].astype(float), [[uy], [ux]], order=1)[0]
+            assert got[c] == pytest.approx(want, abs=1e-9)
+    # inclusive borders; outside is invalid
+    assert O.bilinear(img, 8.0, 6.0) is not None
+    assert O.bilinear(img, 0.0, 0.0) is not None
+    assert O.bilinear(img, 8.0 + 1e-9, 3.0) is None
+    assert O.bilinear(img, 3.0, -1e-9) is None
+
+
+def test_merge_running_average_and_cap():
+    """Eqs. (23)-(24) read as a running average with the count capped at 30:
+    k <= 30 merges into an empty pixel give the mean; the count stops at 30."""
+    rng = np.random.default_rng(13)
+    px = np.zeros(4)
+    vals = rng.uniform(0, 255, (40, 3))
+    for k in range(40):
+        px = O.merge(px, vals[k])
+        if k < 30:
+            assert np.allclose(px[:3], vals[:k + 1].mean(0), atol=1e-10)
+        assert px[3] == min(k + 1, 30)
+    # first merge into an empty canvas is the sample itself with weight 1
+    assert np.array_equal(O.merge(np.zeros(4), [1.5, 2.5, 3.5]), [1.5, 2.5, 3.5, 1.0])
+
+
+def test_warp_integer_translation_is_a_shift():
+    """All matches shifted by an integer (dx, dy): the warped image is the
+    frame shifted exactly, and pixels mapped outside stay empty."""
+    rng = np.random.default_rng(14)
+    frame = rng.integers(0, 256, (24, 32, 3), dtype=np.uint8)
+    x = rng.uniform(0, 31, (40, 2))
+    d = np.array([3.0, -2.0])
+    f = O.fit(x, x + d, 32, 24)
+    assert f.status == 0 and f.n_in == 40
+    canvas = np.zeros((30, 40, 4))
+    rc, cv, valid = O.warp(x, f.scale, f.q, f.mask, f.alpha, frame, canvas,
+                           4, 3, 0, 0, 32, 24)
+    assert rc == 0
+    for k in range(24):
+        for i in range(32):
+            u, v = i + 3, k - 2
+            inside = 0 <= u <= 31 and 0 <= v <= 23
+            on_border = u in (0, 31) or v in (0, 23)
+            if not on_border:          # a border sample may round either way
+                assert valid[k, i] == inside
+            px = cv[k + 3, i + 4]
+            if valid[k, i]:
+                assert np.allclose(px[:3], frame[v, u], atol=1e-6) and px[3] == 1.0
+            else:
+                assert np.array_equal(px, [0, 0, 0, 0])
+
+
+def test_warp_rejects_rect_outside_canvas():
+    x = np.array([[0.0, 0.0], [5.0, 5.0]])
+    q = np.array([O.dq_from_rt(0, 0, 0)] * 2)
+    frame = np.zeros((8, 8, 3), np.uint8)
+    rc, _, _ = O.warp(x, np.ones(2), q, np.ones(2, np.uint8), 1e-3, frame,
+                      np.zeros((8, 8, 4)), 1, 0, 0, 0, 8, 8)
+    assert rc == O.EINVAL
