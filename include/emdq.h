@@ -1,0 +1,175 @@
+/*
+ * emdq.h -- C-ABI of the EMDQ dense deformation field + warp library for the
+ * AMD MI355X (gfx950), libemdq.so.
+ *
+ * Method: H. Zhou and J. Jayender, "Real-time Nonrigid Mosaicking of
+ * Laparoscopy Images" (arXiv 2103.07414).  The input of EMDQ is the
+ * coordinates of feature matches and its output is a dense deformation field
+ * (Sec. II); every pixel is then mapped between the new frame and the mosaic
+ * and its colour merged (Sec. III-F).
+ *
+ * What the library computes (all on the GPU, FP32 unless stated):
+ *   emdq_fit    per-match weighted similarity fits stored as planar dual
+ *               quaternions (DQs) (Eqs. (1), (18)-(20)), with EM inlier
+ *               reweighting over the N x N Gaussian match-weight matrix of
+ *               Eq. (4) (Sec. II-A);
+ *   emdq_field  per-pixel DQ blending of the inlier fits (Eqs. (2)-(4)), DQ
+ *               normalisation, and Eq. (1): F(z) = s (R z + t);
+ *   emdq_warp   emdq_field fused with a bilinear sample of the new frame at
+ *               F(z) and the running-average colour merge of Eqs. (23)-(24)
+ *               into an RGBA FP32 canvas (weight cap 30).
+ *
+ * Conventions
+ *   Coordinates are pixels (x = column, y = row), pixel centres at integers,
+ *   origin at the centre of the top-left pixel.  "src" points live in the
+ *   reference / mosaic frame (x_0 of Eq. (1)), "dst" points in the new frame
+ *   (x_t).  The field maps src -> dst; warping gathers: for every src grid
+ *   point z, the new frame is sampled at F(z).
+ *   A planar DQ is (q_c, q_s, q_x, q_y) = (cos(theta/2), sin(theta/2),
+ *   (cos(theta/2) t_x + sin(theta/2) t_y)/2, (cos(theta/2) t_y -
+ *   sin(theta/2) t_x)/2): the four non-zero components of r + eps t r / 2
+ *   for a rotation about z (footnote to Eq. (1)).
+ *
+ * Memory and streams
+ *   Every buffer argument is a device pointer unless marked "host".  The
+ *   caller owns all buffers; the library owns the model, whose device memory
+ *   is allocated once by emdq_model_create and freed by emdq_model_free.  No
+ *   other call allocates.  All work is enqueued on the caller's stream in
+ *   order; a model must not be used from two streams at once.  Calls are
+ *   deterministic: the same inputs give bit-identical outputs.
+ *
+ * Errors
+ *   Every call returns an emdq_status; nothing else crosses the ABI.
+ *   Argument errors are detected on the host before anything is enqueued.
+ *   Conditions only the GPU can see (non-finite match coordinates, an empty
+ *   inlier set, EM stopped at max_iter) are recorded in the model and
+ *   returned by emdq_model_status, which waits for the stream.  After such
+ *   an error, emdq_field writes NaN and emdq_warp leaves the canvas as is.
+ */
+#ifndef EMDQ_H
+#define EMDQ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EMDQ_OK = 0,
+    EMDQ_WARN_NOT_CONVERGED = 1, /* EM hit max_iter; the results are valid */
+    EMDQ_EINVAL = -1,            /* bad argument (null, size, range)        */
+    EMDQ_ETOOFEW = -2,           /* fewer than 2 matches                    */
+    EMDQ_ENOINLIERS = -3,        /* EM kept no inlier                       */
+    EMDQ_ENONFINITE = -4,        /* NaN or Inf in the match coordinates     */
+    EMDQ_EHIP = -5,              /* a HIP runtime call failed               */
+    EMDQ_ENOMEM = -6             /* device allocation failed                */
+} emdq_status;
+
+/* Tunables of the fit.  alpha0 is the coefficient of Eq. (4) at the
+ * reference resolution ref_w x ref_h (Sec. III-G: 2e-4 at 480 x 270); the
+ * library multiplies it by 1/s^2 with s = (w/ref_w + h/ref_h)/2 for a frame
+ * of w x h.  EM: at most max_iter iterations; a match is an inlier when its
+ * posterior exceeds p_thresh; the inlier fraction is clamped to
+ * [gamma_min, gamma_max] and the inlier variance floored at sigma2_min
+ * (px^2). */
+typedef struct {
+    float alpha0;
+    int ref_w, ref_h;
+    int max_iter;
+    float p_thresh;
+    float gamma_min, gamma_max;
+    float sigma2_min;
+    unsigned flags;   /* reserved, must be 0 */
+} emdq_params;
+
+typedef struct emdq_model_s *emdq_model;
+
+/* Fills the defaults: 2e-4, 480, 270, 50, 0.5, 0.05, 0.95, 1e-2, 0. */
+void emdq_params_default(emdq_params *p);
+
+/* Sec. III-G: alpha0 / s^2, s = (w/ref_w + h/ref_h)/2.  Host function. */
+float emdq_alpha(const emdq_params *p, int frame_w, int frame_h);
+
+/* Allocates a model for up to n_max matches (device memory ~ 100 B per
+ * match plus a few KB) on the current device.  *out receives the handle.
+ * EINVAL if out is null or n_max < 2; ENOMEM / EHIP on allocation failure. */
+emdq_status emdq_model_create(int n_max, emdq_model *out);
+
+/* Releases the model and its device memory (waits for its last stream).
+ * Null is ignored. */
+void emdq_model_free(emdq_model m);
+
+/* EMDQ fit (Sec. II-A; Eqs. (1), (4), (18)-(20)).
+ *   src_xy  device float[n][2]: match positions in the reference frame (x_0)
+ *   dst_xy  device float[n][2]: matched positions in the new frame (x_t)
+ *   n       number of matches, 2 <= n <= n_max of the model
+ *   frame_w, frame_h  size of the new frame (alpha scaling and the uniform
+ *           outlier density 1/(w h))
+ *   params  host pointer, null for the defaults
+ * The inputs are copied into the model, so the caller may reuse them after
+ * the call returns.  The fit runs on `stream`; it synchronises the stream a
+ * few times to read the EM stop flag.  Returns EINVAL (null pointer, bad
+ * size or params), ETOOFEW (n < 2), EHIP, or OK once the fit is enqueued;
+ * its outcome is returned by emdq_model_status. */
+emdq_status emdq_fit(emdq_model m, const float *src_xy, const float *dst_xy, int n,
+                     int frame_w, int frame_h, const emdq_params *params,
+                     hipStream_t stream);
+
+/* Loads per-node warp functions directly (Eq. (1) per node, as the SLAM
+ * nodes of Sec. III carry them) instead of fitting: host arrays
+ *   x_xy float[n][2] node positions at time 0, scale float[n],
+ *   q float[n][4] planar DQs, mask uint8[n] (nullable: all nodes used),
+ *   alpha the already-scaled coefficient of Eq. (4).
+ * Enqueued on `stream` (host arrays are copied before the call returns).
+ * EINVAL on null arrays, n < 1, n > n_max or alpha <= 0. */
+emdq_status emdq_model_set_nodes(emdq_model m, const float *x_xy, const float *scale,
+                                 const float *q, const uint8_t *mask, int n, float alpha,
+                                 hipStream_t stream);
+
+/* Dense field (Eqs. (2)-(4), DQ normalisation, Eq. (1)) at the grid points
+ * z = (zx0 + i, zy0 + k), 0 <= i < w, 0 <= k < h, of the reference frame.
+ *   out_xy  device float[h][w][2], F(z) in new-frame pixels.
+ * EINVAL on a null model/output or w, h < 0 (w or h == 0 is a no-op). */
+emdq_status emdq_field(emdq_model m, int zx0, int zy0, int w, int h, float *out_xy,
+                       hipStream_t stream);
+
+/* Fused field + bilinear warp + colour merge (Sec. III-F, Eqs. (23)-(24)).
+ * For every src grid point z = (zx0 + i, zy0 + k) (0 <= i < w, 0 <= k < h):
+ * u = F(z); when 0 <= u_x <= fw-1 and 0 <= u_y <= fh-1 the new frame is
+ * sampled bilinearly at u (channels 0..255 as reals) and merged into canvas
+ * pixel (ox + z_x, oy + z_y):  rgb <- (A rgb + v) / (A + 1),
+ * A <- min(A + 1, 30), with A the canvas alpha channel; other pixels are left
+ * unchanged.
+ *   frame_rgb  device uint8, row r at frame_rgb + r * frame_pitch_bytes,
+ *              3 bytes (R, G, B) per pixel
+ *   canvas     device float RGBA, pixel (cx, cy) at
+ *              canvas + 4 * (cy * canvas_pitch_px + cx), 16-byte aligned
+ * EINVAL on null pointers, non-positive frame or canvas sizes, a pitch too
+ * small for its row, a misaligned canvas, or a target rectangle that leaves
+ * the canvas. */
+emdq_status emdq_warp(emdq_model m, const uint8_t *frame_rgb, int fw, int fh,
+                      int frame_pitch_bytes, float *canvas, int cw, int ch,
+                      int canvas_pitch_px, int ox, int oy, int zx0, int zy0, int w, int h,
+                      hipStream_t stream);
+
+/* Waits for `stream` and returns the outcome of the last fit or
+ * set_nodes: OK, WARN_NOT_CONVERGED, ENONFINITE, ENOINLIERS. */
+emdq_status emdq_model_status(emdq_model m, hipStream_t stream);
+
+/* Waits for `stream` and copies the fit to host arrays (each nullable):
+ *   scale float[n], q float[n][4], p float[n] posteriors, mask uint8[n],
+ *   n_in inliers, iters EM iterations, sigma2 inlier variance (px^2),
+ *   gamma inlier fraction.  Returns the model status, or EINVAL. */
+emdq_status emdq_model_results(emdq_model m, float *scale, float *q, float *p,
+                               uint8_t *mask, int *n_in, int *iters, float *sigma2,
+                               float *gamma, hipStream_t stream);
+
+/* Static, human-readable name of a status code. */
+const char *emdq_status_string(emdq_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMDQ_H */

@@ -1,0 +1,239 @@
+"""Thin ctypes binding of libemdq.so (C-ABI in include/emdq.h).
+
+Argument marshalling only: every step of the EMDQ path runs in the library's
+HIP kernels.  Device buffers are torch CUDA tensors (PyTorch is used for
+device memory and streams); their data pointers and the current stream are
+handed to the C functions of the same names.  There is no CPU fallback: if
+the library is missing, importing the functions fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libemdq.so")
+
+OK, WARN_NOT_CONVERGED, EINVAL, ETOOFEW, ENOINLIERS, ENONFINITE, EHIP, ENOMEM = \
+    0, 1, -1, -2, -3, -4, -5, -6
+
+# every function declared in include/emdq.h
+EXPORTS = ("emdq_params_default", "emdq_alpha", "emdq_model_create", "emdq_model_free",
+           "emdq_fit", "emdq_model_set_nodes", "emdq_field", "emdq_warp",
+           "emdq_model_status", "emdq_model_results", "emdq_status_string")
+
+
+class Params(C.Structure):
+    """emdq_params."""
+    _fields_ = [("alpha0", C.c_float), ("ref_w", C.c_int), ("ref_h", C.c_int),
+                ("max_iter", C.c_int), ("p_thresh", C.c_float), ("gamma_min", C.c_float),
+                ("gamma_max", C.c_float), ("sigma2_min", C.c_float), ("flags", C.c_uint)]
+
+
+class EmdqError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libemdq.so not found at {LIB_PATH}; build it with "
+                               "__graft_entry__.build() (there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        I, F, P, U8P = C.c_int, C.c_float, C.c_void_p, C.c_void_p
+        L.emdq_params_default.argtypes = [C.POINTER(Params)]
+        L.emdq_params_default.restype = None
+        L.emdq_alpha.argtypes = [C.POINTER(Params), I, I]
+        L.emdq_alpha.restype = F
+        L.emdq_model_create.argtypes = [I, C.POINTER(P)]
+        L.emdq_model_create.restype = I
+        L.emdq_model_free.argtypes = [P]
+        L.emdq_model_free.restype = None
+        L.emdq_fit.argtypes = [P, P, P, I, I, I, C.POINTER(Params), P]
+        L.emdq_fit.restype = I
+        L.emdq_model_set_nodes.argtypes = [P, P, P, P, P, I, F, P]
+        L.emdq_model_set_nodes.restype = I
+        L.emdq_field.argtypes = [P, I, I, I, I, P, P]
+        L.emdq_field.restype = I
+        L.emdq_warp.argtypes = [P, U8P, I, I, I, P, I, I, I, I, I, I, I, I, I, P]
+        L.emdq_warp.restype = I
+        L.emdq_model_status.argtypes = [P, P]
+        L.emdq_model_status.restype = I
+        L.emdq_model_results.argtypes = [P, P, P, P, P, C.POINTER(I), C.POINTER(I),
+                                         C.POINTER(F), C.POINTER(F), P]
+        L.emdq_model_results.restype = I
+        L.emdq_status_string.argtypes = [I]
+        L.emdq_status_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().emdq_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str, allow_warn: bool = True) -> int:
+    if status < 0 or (status > 0 and not allow_warn):
+        raise EmdqError(status, where)
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def emdq_params_default() -> Params:
+    p = Params()
+    lib().emdq_params_default(C.byref(p))
+    return p
+
+
+def emdq_alpha(params: Params | None, frame_w: int, frame_h: int) -> float:
+    return lib().emdq_alpha(C.byref(params) if params is not None else None, frame_w, frame_h)
+
+
+def emdq_model_create(n_max: int) -> int:
+    h = C.c_void_p()
+    _check(lib().emdq_model_create(int(n_max), C.byref(h)), "emdq_model_create")
+    return h.value
+
+
+def emdq_model_free(model: int) -> None:
+    lib().emdq_model_free(model)
+
+
+def emdq_fit(model: int, src, dst, frame_w: int, frame_h: int, params: Params | None = None,
+             stream=None) -> int:
+    """src, dst: CUDA float32 [N, 2].  Returns the enqueue status."""
+    import torch
+    if src.shape != dst.shape or src.dim() != 2 or src.shape[1] != 2:
+        raise ValueError("src and dst must both be [N, 2]")
+    ps = _dev(src, torch.float32, "src")
+    pd = _dev(dst, torch.float32, "dst")
+    return _check(lib().emdq_fit(model, ps, pd, int(src.shape[0]), int(frame_w), int(frame_h),
+                                 C.byref(params) if params is not None else None,
+                                 _stream(stream)), "emdq_fit")
+
+
+def emdq_model_set_nodes(model: int, x_xy, scale, q, mask, alpha: float, stream=None) -> int:
+    """Host (numpy) arrays: x_xy [N, 2], scale [N], q [N, 4] float32, mask [N] uint8."""
+    import numpy as np
+    x = np.ascontiguousarray(x_xy, dtype=np.float32)
+    s = np.ascontiguousarray(scale, dtype=np.float32)
+    qq = np.ascontiguousarray(q, dtype=np.float32)
+    n = x.shape[0]
+    if x.shape != (n, 2) or s.shape != (n,) or qq.shape != (n, 4):
+        raise ValueError("shapes must be x [N,2], scale [N], q [N,4]")
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    if m is not None and m.shape != (n,):
+        raise ValueError("mask must be [N]")
+    return _check(lib().emdq_model_set_nodes(
+        model, x.ctypes.data, s.ctypes.data, qq.ctypes.data,
+        None if m is None else m.ctypes.data, n, float(alpha), _stream(stream)),
+        "emdq_model_set_nodes")
+
+
+def emdq_field(model: int, zx0: int, zy0: int, w: int, h: int, out, stream=None) -> int:
+    """out: CUDA float32 [h, w, 2]."""
+    import torch
+    if tuple(out.shape) != (h, w, 2):
+        raise ValueError("out must be [h, w, 2]")
+    po = _dev(out, torch.float32, "out")
+    return _check(lib().emdq_field(model, zx0, zy0, w, h, po, _stream(stream)), "emdq_field")
+
+
+def emdq_warp(model: int, frame, canvas, ox: int, oy: int, zx0: int, zy0: int, w: int, h: int,
+              stream=None) -> int:
+    """frame: CUDA uint8 [fh, fw, 3]; canvas: CUDA float32 [ch, cw, 4] (updated)."""
+    import torch
+    if frame.dim() != 3 or frame.shape[2] != 3:
+        raise ValueError("frame must be [fh, fw, 3]")
+    if canvas.dim() != 3 or canvas.shape[2] != 4:
+        raise ValueError("canvas must be [ch, cw, 4]")
+    pf = _dev(frame, torch.uint8, "frame")
+    pc = _dev(canvas, torch.float32, "canvas")
+    fh, fw = int(frame.shape[0]), int(frame.shape[1])
+    ch, cw = int(canvas.shape[0]), int(canvas.shape[1])
+    return _check(lib().emdq_warp(model, pf, fw, fh, 3 * fw, pc, cw, ch, cw, ox, oy, zx0, zy0,
+                                  w, h, _stream(stream)), "emdq_warp")
+
+
+def emdq_model_status(model: int, stream=None) -> int:
+    return lib().emdq_model_status(model, _stream(stream))
+
+
+def emdq_model_results(model: int, n: int, stream=None) -> dict:
+    """Copies the fit to numpy arrays (waits for the stream)."""
+    import numpy as np
+    scale = np.zeros(n, np.float32)
+    q = np.zeros((n, 4), np.float32)
+    p = np.zeros(n, np.float32)
+    mask = np.zeros(n, np.uint8)
+    n_in, iters = C.c_int(), C.c_int()
+    s2, g = C.c_float(), C.c_float()
+    st = lib().emdq_model_results(model, scale.ctypes.data, q.ctypes.data, p.ctypes.data,
+                                  mask.ctypes.data, C.byref(n_in), C.byref(iters), C.byref(s2),
+                                  C.byref(g), _stream(stream))
+    return dict(status=st, scale=scale, q=q, p=p, mask=mask, n_in=n_in.value,
+                iters=iters.value, sigma2=s2.value, gamma=g.value)
+
+
+class Model:
+    """Owns an emdq_model handle."""
+
+    def __init__(self, n_max: int):
+        self.handle = emdq_model_create(n_max)
+        self.n = 0
+
+    def fit(self, src, dst, frame_w, frame_h, params=None, stream=None):
+        self.n = int(src.shape[0])
+        return emdq_fit(self.handle, src, dst, frame_w, frame_h, params, stream)
+
+    def set_nodes(self, x_xy, scale, q, mask, alpha, stream=None):
+        self.n = int(len(scale))
+        return emdq_model_set_nodes(self.handle, x_xy, scale, q, mask, alpha, stream)
+
+    def field(self, zx0, zy0, w, h, out, stream=None):
+        return emdq_field(self.handle, zx0, zy0, w, h, out, stream)
+
+    def warp(self, frame, canvas, ox, oy, zx0, zy0, w, h, stream=None):
+        return emdq_warp(self.handle, frame, canvas, ox, oy, zx0, zy0, w, h, stream)
+
+    def status(self, stream=None):
+        return emdq_model_status(self.handle, stream)
+
+    def results(self, stream=None):
+        return emdq_model_results(self.handle, self.n, stream)
+
+    def close(self):
+        if self.handle:
+            emdq_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,55 @@
+"""The C-ABI library loads on the host and exports every function the header
+declares; host-only calls (no device work) behave as documented."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "emdq.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(emdq_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_2103_07414_amd import emdq as E
+    L = E.lib()
+    names = header_functions()
+    assert len(names) == 11
+    assert sorted(E.EXPORTS) == names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_host_only_calls():
+    from paper_2103_07414_amd import emdq as E
+    p = E.emdq_params_default()
+    assert (p.alpha0, p.ref_w, p.ref_h, p.max_iter) == (np.float32(2e-4), 480, 270, 50)
+    assert (p.gamma_min, p.gamma_max, p.flags) == (np.float32(0.05), np.float32(0.95), 0)
+    for w, h in [(320, 240), (1280, 1024), (1920, 1080), (480, 270)]:
+        assert E.emdq_alpha(p, w, h) == np.float32(O.alpha(w, h))
+    assert E.emdq_alpha(None, 0, 5) == 0.0
+    assert E.status_string(E.ENONFINITE) == "non-finite match coordinates"
+    assert E.status_string(99) == "unknown status"
+    L = E.lib()
+    h = C.c_void_p()
+    assert L.emdq_model_create(1, C.byref(h)) == E.EINVAL      # n_max < 2
+    assert L.emdq_model_create(4, None) == E.EINVAL
+    assert L.emdq_fit(None, None, None, 4, 10, 10, None, None) == E.EINVAL
+    assert L.emdq_field(None, 0, 0, 1, 1, None, None) == E.EINVAL
+    assert L.emdq_model_status(None, None) == E.EINVAL
+    L.emdq_model_free(None)
+
+
+def test_binding_has_no_cpu_path():
+    """The binding refuses to run without the built library."""
+    from paper_2103_07414_amd import emdq as E
+    src = open(E.__file__).read()
+    assert "oracle" not in src.replace("there is no CPU fallback", "")
