@@ -30,12 +30,15 @@ class Params(C.Structure):
 
 
 def lib():
-    """Load the oracle library, building it first if it is missing."""
+    """Load the oracle library, building it first if it is missing.
+    ORACLE_LIB may name another build of emdq_oracle.c (the mutation test
+    uses it to load copies with planted mistakes)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("ORACLE_LIB", _build.LIB)
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         I, Dd = C.c_int, C.c_double
         L.oracle_params_default.argtypes = [C.POINTER(Params)]
         L.oracle_alpha.restype = Dd
