@@ -67,6 +67,9 @@ def lib():
         L.oracle_bilinear.restype = I
         L.oracle_bilinear.argtypes = [_U8, I, I, I, Dd, Dd, _D]
         L.oracle_merge.argtypes = [_D, _D]
+        L.oracle_dq_then.argtypes = [_D, _D, _D]
+        L.oracle_update.argtypes = [Dd, _D, Dd, _D, C.POINTER(Dd), _D]
+        L.oracle_uncertainty.argtypes = [I, _D, _U8, Dd, I, I, I, I, _D]
         L.oracle_warp.restype = I
         L.oracle_warp.argtypes = [I, _D, _D, _D, _U8, Dd, _U8, I, I, I, _D, I, I, I,
                                   I, I, I, I, I, I, C.c_void_p]
@@ -230,3 +233,27 @@ def warp(x, s, q, mask, alpha_, frame, canvas, ox: int, oy: int, zx0: int, zy0: 
                            cw, ch, cw, ox, oy, zx0, zy0, w, h,
                            valid.ctypes.data_as(C.c_void_p))
     return rc, cv, valid
+
+
+def dq_then(a, b):
+    """The motion applying a first, then b (the "*" of App. A)."""
+    out = np.zeros(4)
+    lib().oracle_dq_then(_d(a, (4,)), _d(b, (4,)), out)
+    return out
+
+
+def update(s_old, q_old, ds, dq):
+    """App. A warp-function update -> (s_new, q_new)."""
+    s_new = C.c_double()
+    q_new = np.zeros(4)
+    lib().oracle_update(s_old, _d(q_old, (4,)), ds, _d(dq, (4,)), C.byref(s_new), q_new)
+    return s_new.value, q_new
+
+
+def uncertainty(x, mask, beta, zx0, zy0, w, h):
+    """Eq. (8) at the grid points -> [h, w]."""
+    x = _d(x)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    out = np.zeros((h, w))
+    lib().oracle_uncertainty(mask.shape[0], x, mask, beta, zx0, zy0, w, h, out)
+    return out

@@ -19,6 +19,9 @@
  *   Sec. III-G    alpha = 2e-4 scaled by 1/s^2, s = (w/480 + h/270)/2.
  *   Sec. II-A     EMDQ: mismatch removal by expectation maximisation plus a
  *                 smooth DQ field interpolated among the inliers.
+ *   Eq. (8)       uncertainty of the field: exp(beta d^2) to the nearest inlier.
+ *   App. A        update of a node's warp function by a new (scale, DQ) that
+ *                 is expressed in the current frame.
  *
  * The paper treats EMDQ as a black box and gives its inner rules elsewhere,
  * so the EM part follows this reading (it is the contract the GPU library is
@@ -444,4 +447,68 @@ int oracle_warp(int n, const double *x, const double *scale, const double *q,
         }
     free(wt);
     return bad ? OR_ENOINLIERS : OR_OK;
+}
+
+/* ------------------------------------------- App. A, Eq. (8): node state --- */
+
+/* Planar DQ of a pure translation t (trans2dq of App. A). */
+void oracle_dq_translation(double tx, double ty, double q[4])
+{
+    oracle_dq_from_rt(0.0, tx, ty, q);
+}
+
+/* Rigid motion of a planar DQ as (cos, sin, tx, ty); q need not be unit. */
+static void rigid_of(const double q[4], double m[4])
+{
+    oracle_dq_decode(q, &m[0], &m[1], &m[2], &m[3]);
+}
+
+/* a * b in the sense of App. A: the motion that applies a first, then b. */
+void oracle_dq_then(const double a[4], const double b[4], double out[4])
+{
+    double ma[4], mb[4];
+    rigid_of(a, ma);
+    rigid_of(b, mb);
+    /* b(a(x)) = Rb (Ra x + ta) + tb */
+    double c = mb[0] * ma[0] - mb[1] * ma[1];
+    double s = mb[1] * ma[0] + mb[0] * ma[1];
+    double tx = mb[0] * ma[2] - mb[1] * ma[3] + mb[2];
+    double ty = mb[1] * ma[2] + mb[0] * ma[3] + mb[3];
+    oracle_dq_from_rt(atan2(s, c), tx, ty, out);
+}
+
+/* App. A warp-function update f(s_old, q_old, ds, dq):
+ *   q1 = trans2dq((1 - s_old) / s_old * dt),  q2 = dq * q1,
+ *   q_new = q_old * q2,  s_new = ds * s_old,
+ * with dt the translation of dq and "*" applying its left operand first. */
+void oracle_update(double s_old, const double q_old[4], double ds, const double dq[4],
+                   double *s_new, double q_new[4])
+{
+    double md[4], q1[4], q2[4];
+    rigid_of(dq, md);
+    double k = (1.0 - s_old) / s_old;
+    oracle_dq_translation(k * md[2], k * md[3], q1);
+    oracle_dq_then(dq, q1, q2);
+    oracle_dq_then(q_old, q2, q_new);
+    *s_new = ds * s_old;
+}
+
+/* Eq. (8): uncertainty at the grid points z = (zx0 + i, zy0 + k):
+ * min over the inliers j of exp(beta |z - x_j|^2).  out [h][w]; +inf when
+ * there is no inlier. */
+void oracle_uncertainty(int n, const double *x, const uint8_t *mask, double beta, int zx0,
+                        int zy0, int w, int h, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < h; ++k)
+        for (int i = 0; i < w; ++i) {
+            double best = INFINITY;
+            for (int j = 0; j < n; ++j) {
+                if (!mask[j]) continue;
+                double dx = zx0 + i - x[2 * j], dy = zy0 + k - x[2 * j + 1];
+                double u = exp(beta * (dx * dx + dy * dy));
+                if (u < best) best = u;
+            }
+            out[(size_t)k * w + i] = best;
+        }
 }

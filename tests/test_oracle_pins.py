@@ -480,3 +480,59 @@ def test_warp_rejects_rect_outside_canvas():
     rc, _, _ = O.warp(x, np.ones(2), q, np.ones(2, np.uint8), 1e-3, frame,
                       np.zeros((8, 8, 4)), 1, 0, 0, 0, 8, 8)
     assert rc == O.EINVAL
+
+
+# ------------------------------------------- App. A update, Eq. (8) ---------
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_update_satisfies_app_a_requirement(seed):
+    """App. A: with x1 = s_old q_old(x0), the update must give
+    s_new q_new(x0) = ds dq(x1) for every point."""
+    rng = np.random.default_rng(seed)
+    s_old, ds = rng.uniform(0.8, 1.25, 2)
+    q_old = O.dq_from_rt(rng.uniform(-1, 1), *rng.uniform(-50, 50, 2))
+    dq = O.dq_from_rt(rng.uniform(-0.5, 0.5), *rng.uniform(-20, 20, 2))
+    s_new, q_new = O.update(s_old, q_old, ds, dq)
+    for x0 in rng.uniform(-300, 300, (5, 2)):
+        x1 = O.warp_point(s_old, q_old, *x0)
+        want = O.warp_point(ds, dq, *x1)
+        got = O.warp_point(s_new, q_new, *x0)
+        assert np.allclose(got, want, atol=1e-9)
+
+
+def test_dq_then_is_composition_and_matches_full_dq_product():
+    """'*' applies its left operand first: a * b = b o a, which is the
+    full-DQ product b (x) a."""
+    mp.mp.dps = 50
+    a = (0.4, 10.0, -3.0)
+    b = (-0.9, 2.0, 7.0)
+    qa, qb = O.dq_from_rt(*a), O.dq_from_rt(*b)
+    c = O.dq_then(qa, qb)
+    ra, da = dq_full(mp.mpf(a[0]), mp.mpf(a[1]), mp.mpf(a[2]))
+    rb, db = dq_full(mp.mpf(b[0]), mp.mpf(b[1]), mp.mpf(b[2]))
+    r = qmul(rb, ra)                                   # real part of qb qa
+    d = tuple(x + y for x, y in zip(qmul(rb, da), qmul(db, ra)))
+    sgn = 1 if r[0] >= 0 else -1                        # canonical q_c >= 0
+    want = [sgn * float(r[0]), sgn * float(r[3]), sgn * float(d[1]), sgn * float(d[2])]
+    assert np.allclose(c, want, atol=1e-12)
+
+
+def test_uncertainty_is_exp_of_nearest_inlier_distance():
+    """Eq. (8): min_j exp(beta d^2) = exp(beta d_min^2) with d_min the
+    distance to the nearest inlier (scipy KD-tree); outliers are ignored."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 60, (30, 2))
+    mask = (rng.uniform(size=30) > 0.3).astype(np.uint8)
+    beta = 3e-3 / ((64 / 480 + 48 / 270) / 2) ** 2
+    U = O.uncertainty(x, mask, beta, -4, -3, 70, 55)
+    gy, gx = np.mgrid[-3:52, -4:66]
+    d, _ = cKDTree(x[mask.astype(bool)]).query(np.stack([gx.ravel(), gy.ravel()], 1))
+    assert np.allclose(U.ravel(), np.exp(beta * d ** 2), rtol=1e-12)
+    # at an inlier the uncertainty is exactly 1
+    j = int(np.flatnonzero(mask)[0])
+    xi = np.round(x[j]).astype(int)
+    x2 = x.copy()
+    x2[j] = xi
+    U2 = O.uncertainty(x2, mask, beta, int(xi[0]), int(xi[1]), 1, 1)
+    assert U2[0, 0] == 1.0
