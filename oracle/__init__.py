@@ -70,6 +70,10 @@ def lib():
         L.oracle_dq_then.argtypes = [_D, _D, _D]
         L.oracle_update.argtypes = [Dd, _D, Dd, _D, C.POINTER(Dd), _D]
         L.oracle_uncertainty.argtypes = [I, _D, _U8, Dd, I, I, I, I, _D]
+        L.oracle_blend_dq.restype = I
+        L.oracle_blend_dq.argtypes = [I, _D, _D, _D, _U8, Dd, Dd, Dd, C.POINTER(Dd), _D]
+        L.oracle_track_nodes.restype = I
+        L.oracle_track_nodes.argtypes = [I, _D, _D, _D, _U8, Dd, Dd, I, _D, _D, _D, _D]
         L.oracle_warp.restype = I
         L.oracle_warp.argtypes = [I, _D, _D, _D, _U8, Dd, _U8, I, I, I, _D, I, I, I,
                                   I, I, I, I, I, I, C.c_void_p]
@@ -257,3 +261,28 @@ def uncertainty(x, mask, beta, zx0, zy0, w, h):
     out = np.zeros((h, w))
     lib().oracle_uncertainty(mask.shape[0], x, mask, beta, zx0, zy0, w, h, out)
     return out
+
+
+def blend_dq(x, s, q, mask, alpha_, zx, zy):
+    """Eqs. (2)-(3) at (zx, zy) over the inliers, DQ normalised -> (s, q)."""
+    x, s, q = _d(x), _d(s), _d(q)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    so = C.c_double()
+    qo = np.zeros(4)
+    if lib().oracle_blend_dq(s.shape[0], x, s, q, mask, alpha_, zx, zy, C.byref(so), qo) != 0:
+        raise ValueError("no weight at point")
+    return so.value, qo
+
+
+def track_nodes(x, s, q, mask, alpha_, beta, pos, s_node, q_node, sig2):
+    """One node tracking step (Sec. III-C/E, Eqs. (8)-(9), App. A) on copies
+    of the node arrays -> (status, pos, s_node, q_node, sig2)."""
+    x, s, q = _d(x), _d(s), _d(q)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    pos = np.array(pos, dtype=np.float64, order="C")
+    s_node = np.array(s_node, dtype=np.float64, order="C")
+    q_node = np.array(q_node, dtype=np.float64, order="C")
+    sig2 = np.array(sig2, dtype=np.float64, order="C")
+    rc = lib().oracle_track_nodes(s.shape[0], x, s, q, mask, alpha_, beta, s_node.shape[0],
+                                  pos, s_node, q_node, sig2)
+    return rc, pos, s_node, q_node, sig2

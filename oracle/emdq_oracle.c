@@ -512,3 +512,72 @@ void oracle_uncertainty(int n, const double *x, const uint8_t *mask, double beta
             out[(size_t)k * w + i] = best;
         }
 }
+
+/* Eqs. (2)-(3) at the point z over the inliers (mask), followed by the
+ * normalisation of the blended DQ by the norm of its real part: the
+ * node-level warp increment (Delta s, Delta q) that Sec. III-C reads off the
+ * EMDQ field.  Returns 0, or -1 if no inlier carries weight at z. */
+int oracle_blend_dq(int n, const double *x, const double *scale, const double *q,
+                    const uint8_t *mask, double alpha, double zx, double zy, double *s_out,
+                    double q_out[4])
+{
+    double W = 0.0, sb = 0.0, qb[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < n; ++j) {
+        if (!mask[j]) continue;
+        double dx = zx - x[2 * j], dy = zy - x[2 * j + 1];
+        double w = exp(-alpha * (dx * dx + dy * dy));
+        W += w;
+        sb += w * scale[j];
+        for (int c = 0; c < 4; ++c) qb[c] += w * q[4 * j + c];
+    }
+    if (!(W > 0.0)) return -1;
+    double nr = sqrt(qb[0] * qb[0] + qb[1] * qb[1]);
+    if (!(nr > 0.0)) return -1;
+    *s_out = sb / W;
+    for (int c = 0; c < 4; ++c) q_out[c] = qb[c] / nr;   /* qb / W / (|r| / W) */
+    return 0;
+}
+
+/* One tracking step of the deformation nodes (Sec. III-C, Sec. III-E):
+ * for node i at position p_i in the frame the model's src points live in,
+ *   (ds, dq) = the blend at p_i (Eqs. (2)-(3), normalised),
+ *   dsig2    = min over the inliers j of exp(beta |p_i - x_j|^2)  (Eq. (8)),
+ *   (s, q)  <- f(s, q, ds, dq)                                     (App. A),
+ *   sig2    <- ds^2 sig2 + dsig2                                   (Eq. (9)),
+ *   p_i     <- ds dq(p_i)                                          (Eq. (1)).
+ * Arrays are updated in place.  Returns 0, or OR_ENOINLIERS if some node
+ * has no weight (its entries are then NaN). */
+int oracle_track_nodes(int n, const double *x, const double *scale, const double *q,
+                       const uint8_t *mask, double alpha, double beta, int m, double *pos,
+                       double *s_node, double *q_node, double *sig2)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int i = 0; i < m; ++i) {
+        double px = pos[2 * i], py = pos[2 * i + 1];
+        double ds, dq[4];
+        if (oracle_blend_dq(n, x, scale, q, mask, alpha, px, py, &ds, dq) != 0) {
+            pos[2 * i] = pos[2 * i + 1] = s_node[i] = sig2[i] = NAN;
+            for (int c = 0; c < 4; ++c) q_node[4 * i + c] = NAN;
+            bad = 1;
+            continue;
+        }
+        double u = INFINITY;                     /* Eq. (8) */
+        for (int j = 0; j < n; ++j) {
+            if (!mask[j]) continue;
+            double dx = px - x[2 * j], dy = py - x[2 * j + 1];
+            double e = exp(beta * (dx * dx + dy * dy));
+            if (e < u) u = e;
+        }
+        double s_new, q_new[4];
+        oracle_update(s_node[i], &q_node[4 * i], ds, dq, &s_new, q_new);
+        sig2[i] = ds * ds * sig2[i] + u;
+        double nx, ny;
+        oracle_warp_point(ds, dq, px, py, &nx, &ny);
+        pos[2 * i] = nx;
+        pos[2 * i + 1] = ny;
+        s_node[i] = s_new;
+        for (int c = 0; c < 4; ++c) q_node[4 * i + c] = q_new[c];
+    }
+    return bad ? OR_ENOINLIERS : OR_OK;
+}

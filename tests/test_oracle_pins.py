@@ -536,3 +536,74 @@ def test_uncertainty_is_exp_of_nearest_inlier_distance():
     x2[j] = xi
     U2 = O.uncertainty(x2, mask, beta, int(xi[0]), int(xi[1]), 1, 1)
     assert U2[0, 0] == 1.0
+
+
+# ---------------------------------------------- node tracking (Sec. III) ---
+
+def _beta(w, h):
+    g = json.load(open(os.path.join(GOLDEN, "paper_parameters.json")))
+    rw, rh = g["reference_resolution"]["value"]
+    s = (w / rw + h / rh) / 2
+    return g["beta"]["value"] / s ** 2
+
+
+def test_blend_dq_against_full_dq_brute_force():
+    """Eqs. (2)-(3) + normalisation at 50 digits on full 8-component DQs:
+    the oracle's (s, q) applied by Eq. (1) reproduces the brute-force warp,
+    and its real part is unit."""
+    mp.mp.dps = 50
+    rng = np.random.default_rng(41)
+    n = 6
+    x = rng.uniform(0, 80, (n, 2))
+    th = rng.uniform(-0.3, 0.3, n)
+    ts = rng.uniform(-20, 20, (n, 2))
+    sc = rng.uniform(0.9, 1.1, n)
+    q = np.array([O.dq_from_rt(a, *t) for a, t in zip(th, ts)])
+    mask = np.array([1, 1, 0, 1, 1, 1], np.uint8)
+    alpha = 7e-4
+    for zx, zy in [(10.0, 70.0), (44.5, 3.25), (79.0, 79.0)]:
+        s, qb = O.blend_dq(x, sc, q, mask, alpha, zx, zy)
+        assert abs(qb[0] ** 2 + qb[1] ** 2 - 1) < 1e-14
+        want = blend_full(x, sc, th, ts, mask.astype(float), alpha, zx, zy)
+        assert np.allclose(O.warp_point(s, qb, zx, zy), want, atol=1e-9)
+
+
+def test_track_nodes_single_similarity():
+    """Model = one similarity T everywhere.  Every node moves by T (Eq. (1)),
+    its new warp function satisfies the App. A requirement from its time-0
+    position, and Eq. (9) with Eq. (8) gives s_T^2 sig2 + exp(beta d_min^2)
+    with d_min from a KD-tree (scipy)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(42)
+    n = 60
+    x = rng.uniform(0, 300, (n, 2))
+    sT, qT = 1.03, O.dq_from_rt(0.05, 4.0, -6.0)
+    sc = np.full(n, sT)
+    q = np.tile(qT, (n, 1))
+    mask = (rng.uniform(size=n) > 0.25).astype(np.uint8)
+    alpha, beta = O.alpha(320, 240), _beta(320, 240)
+    m = 25
+    x0 = rng.uniform(0, 300, (m, 2))
+    s_old = rng.uniform(0.9, 1.1, m)
+    q_old = np.array([O.dq_from_rt(a, *t) for a, t in
+                      zip(rng.uniform(-0.2, 0.2, m), rng.uniform(-15, 15, (m, 2)))])
+    pos = np.array([O.warp_point(s_old[i], q_old[i], *x0[i]) for i in range(m)])
+    sig2 = rng.uniform(0, 3, m)
+    rc, pos1, s1, q1, sig21 = O.track_nodes(x, sc, q, mask, alpha, beta, pos, s_old, q_old,
+                                            sig2)
+    assert rc == 0
+    want_pos = np.array([O.warp_point(sT, qT, *p) for p in pos])
+    assert np.allclose(pos1, want_pos, atol=1e-9)
+    for i in range(m):
+        assert np.allclose(O.warp_point(s1[i], q1[i], *x0[i]), want_pos[i], atol=1e-9)
+    assert np.allclose(s1, sT * s_old, rtol=1e-13)
+    d, _ = cKDTree(x[mask.astype(bool)]).query(pos)
+    assert np.allclose(sig21, sT ** 2 * sig2 + np.exp(beta * d ** 2), rtol=1e-12)
+
+
+def test_track_nodes_no_inliers_is_reported():
+    x = np.zeros((3, 2))
+    rc, pos, s, q, sig2 = O.track_nodes(x, np.ones(3), np.tile([1.0, 0, 0, 0], (3, 1)),
+                                        np.zeros(3, np.uint8), 1e-3, 1e-3, [[1.0, 2.0]],
+                                        [1.0], [[1.0, 0, 0, 0]], [0.0])
+    assert rc == O.ENOINLIERS and np.isnan(pos).all() and np.isnan(sig2).all()
