@@ -60,6 +60,11 @@ def lib():
         L.oracle_fit.restype = I
         L.oracle_fit.argtypes = [I, _D, _D, I, I, C.POINTER(Params), _D, _D, _D, _U8,
                                  C.POINTER(I), C.POINTER(Dd), C.POINTER(Dd)]
+        L.oracle_fit_init.restype = I
+        L.oracle_fit_init.argtypes = [I, _D, _D, I, I, C.POINTER(Params), C.c_void_p, _D, _D,
+                                      _D, _U8, C.POINTER(I), C.POINTER(Dd), C.POINTER(Dd)]
+        L.oracle_init_features.argtypes = [I, _D, _D, Dd, _D]
+        L.oracle_init_mlp.argtypes = [I, _D, _D, _D]
         L.oracle_field.restype = I
         L.oracle_field.argtypes = [I, _D, _D, _D, _U8, Dd, I, I, I, I, _D]
         L.oracle_field_points.restype = I
@@ -178,16 +183,20 @@ class Fit:
         return int(self.mask.sum())
 
 
-def fit(src, dst, frame_w: int, frame_h: int, prm: Params | None = None) -> Fit:
-    """EM fit; src, dst: [N, 2] (float32 inputs are widened exactly)."""
+def fit(src, dst, frame_w: int, frame_h: int, prm: Params | None = None,
+        init_p=None) -> Fit:
+    """EM fit; src, dst: [N, 2] (float32 inputs are widened exactly).
+    init_p: starting posteriors (None: the plain start p = 1)."""
     x, y = _d(src), _d(dst)
     n = x.shape[0]
     prm = prm or params()
     s, q, p = np.zeros(n), np.zeros((n, 4)), np.zeros(n)
     mask = np.zeros(n, dtype=np.uint8)
     it, s2, g = C.c_int(), C.c_double(), C.c_double()
-    rc = lib().oracle_fit(n, x, y, frame_w, frame_h, C.byref(prm), s, q, p, mask,
-                          C.byref(it), C.byref(s2), C.byref(g))
+    ip = None if init_p is None else _d(init_p, (n,))
+    rc = lib().oracle_fit_init(n, x, y, frame_w, frame_h, C.byref(prm),
+                               None if ip is None else ip.ctypes.data_as(C.c_void_p), s, q, p,
+                               mask, C.byref(it), C.byref(s2), C.byref(g))
     a = lib().oracle_alpha(prm.alpha0, prm.ref_w, prm.ref_h, frame_w, frame_h)
     return Fit(rc, s, q, p, mask, it.value, s2.value, g.value, a)
 
@@ -286,3 +295,24 @@ def track_nodes(x, s, q, mask, alpha_, beta, pos, s_node, q_node, sig2):
     rc = lib().oracle_track_nodes(s.shape[0], x, s, q, mask, alpha_, beta, s_node.shape[0],
                                   pos, s_node, q_node, sig2)
     return rc, pos, s_node, q_node, sig2
+
+
+KNN, N_FEAT, N_HIDDEN = 16, 64, 128
+N_WEIGHTS = N_HIDDEN * N_FEAT + N_HIDDEN + N_HIDDEN * N_HIDDEN + N_HIDDEN + N_HIDDEN + 1
+
+
+def init_features(src, dst, alpha_):
+    """kNN features of the learned EM start -> [N, 64]."""
+    x, y = _d(src), _d(dst)
+    out = np.zeros((x.shape[0], N_FEAT))
+    lib().oracle_init_features(x.shape[0], x, y, alpha_, out)
+    return out
+
+
+def init_mlp(feat, weights):
+    """The learned start's network on features [N, 64] -> p [N]."""
+    feat = _d(feat)
+    w = _d(weights, (N_WEIGHTS,))
+    out = np.zeros(feat.shape[0])
+    lib().oracle_init_mlp(feat.shape[0], feat, w, out)
+    return out

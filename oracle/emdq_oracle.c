@@ -286,9 +286,26 @@ static int all_finite(int n, const double *v)
  * Outputs scale[n], q[n][4], p[n], mask[n]; iters, sigma2, gamma (nullable).
  * frame_w, frame_h: size of the new frame (uniform outlier density 1/(w h)
  * and the Sec. III-G alpha scaling). */
+int oracle_fit_init(int n, const double *x, const double *y, int frame_w, int frame_h,
+                    const oracle_params *prm_in, const double *init_p, double *scale,
+                    double *q, double *p, uint8_t *mask, int *iters, double *sigma2_out,
+                    double *gamma_out);
+
 int oracle_fit(int n, const double *x, const double *y, int frame_w, int frame_h,
                const oracle_params *prm_in, double *scale, double *q, double *p,
                uint8_t *mask, int *iters, double *sigma2_out, double *gamma_out)
+{
+    return oracle_fit_init(n, x, y, frame_w, frame_h, prm_in, NULL, scale, q, p, mask, iters,
+                           sigma2_out, gamma_out);
+}
+
+/* EM fit starting from the posteriors init_p (null: p = 1, the plain start).
+ * The starting mask is init_p > p_thresh, decided in FP32 as every later
+ * mask. */
+int oracle_fit_init(int n, const double *x, const double *y, int frame_w, int frame_h,
+                    const oracle_params *prm_in, const double *init_p, double *scale,
+                    double *q, double *p, uint8_t *mask, int *iters, double *sigma2_out,
+                    double *gamma_out)
 {
     oracle_params prm;
     if (prm_in) prm = *prm_in; else oracle_params_default(&prm);
@@ -302,7 +319,16 @@ int oracle_fit(int n, const double *x, const double *y, int frame_w, int frame_h
     double *e2 = (double *)malloc(sizeof(double) * (size_t)n);
     double *pn = (double *)malloc(sizeof(double) * (size_t)n);
     uint8_t *prev = (uint8_t *)malloc((size_t)n);
-    for (int i = 0; i < n; ++i) { p[i] = 1.0; mask[i] = 1; }
+    for (int i = 0; i < n; ++i) {
+        p[i] = init_p ? init_p[i] : 1.0;
+        mask[i] = ((float)p[i] > (float)prm.p_thresh) ? 1 : 0;
+    }
+    if (init_p && !all_finite(n, init_p)) {
+        free(e2);
+        free(pn);
+        free(prev);
+        return OR_EINVAL;
+    }
     int k = 0, converged = 0, status = OR_OK;
     double sigma2 = 0.0, gamma = 0.0;
     while (1) {
@@ -580,4 +606,88 @@ int oracle_track_nodes(int n, const double *x, const double *scale, const double
         for (int c = 0; c < 4; ++c) q_node[4 * i + c] = q_new[c];
     }
     return bad ? OR_ENOINLIERS : OR_OK;
+}
+
+/* ------------------------------------------------ learned EM start --- */
+/*
+ * Not in the paper: a learned starting point for the EM (a per-match
+ * inlier prior), the next step the design takes beyond it.  Definition:
+ *   neighbours  the K = 16 other matches nearest to match i by source
+ *               distance, ordered by (squared distance in FP64, index);
+ *               missing neighbours (n - 1 < K) give zero features;
+ *   features    for neighbour rank r and neighbour j, with g = sqrt(alpha)
+ *               and displacement d = dst - src:
+ *                 f[4r]   = g (x_j - x_i)_x,  f[4r+1] = g (x_j - x_i)_y,
+ *                 f[4r+2] = ss((d_j - d_i)_x / 8),  f[4r+3] = ss((d_j - d_i)_y / 8),
+ *               ss(t) = t / (1 + |t|);
+ *   network     h1 = gelu(W1 f + b1) (128), h2 = gelu(W2 h1 + b2) (128),
+ *               p = sigmoid(w3 . h2 + b3), gelu(t) = t (1 + erf(t / sqrt 2)) / 2.
+ */
+#define OR_KNN 16
+#define OR_NF (4 * OR_KNN)
+#define OR_NH 128
+
+void oracle_init_features(int n, const double *x, const double *y, double alpha,
+                          double *feat)
+{
+    const double g = sqrt(alpha);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i) {
+        double bd[OR_KNN];
+        int bj[OR_KNN];
+        int cnt = 0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[2 * j] - x[2 * i], dy = x[2 * j + 1] - x[2 * i + 1];
+            double d2 = dx * dx + dy * dy;
+            /* insertion into the sorted list of the best K by (d2, j) */
+            int pos = cnt;
+            while (pos > 0 && (bd[pos - 1] > d2 || (bd[pos - 1] == d2 && bj[pos - 1] > j)))
+                --pos;
+            if (pos >= OR_KNN) continue;
+            int last = cnt < OR_KNN ? cnt : OR_KNN - 1;
+            for (int k = last; k > pos; --k) { bd[k] = bd[k - 1]; bj[k] = bj[k - 1]; }
+            bd[pos] = d2;
+            bj[pos] = j;
+            if (cnt < OR_KNN) ++cnt;
+        }
+        double *f = feat + (size_t)i * OR_NF;
+        double dix = y[2 * i] - x[2 * i], diy = y[2 * i + 1] - x[2 * i + 1];
+        for (int r = 0; r < OR_KNN; ++r) {
+            if (r >= cnt) { f[4 * r] = f[4 * r + 1] = f[4 * r + 2] = f[4 * r + 3] = 0.0; continue; }
+            int j = bj[r];
+            double ex = (y[2 * j] - x[2 * j] - dix) / 8.0, ey = (y[2 * j + 1] - x[2 * j + 1] - diy) / 8.0;
+            f[4 * r] = g * (x[2 * j] - x[2 * i]);
+            f[4 * r + 1] = g * (x[2 * j + 1] - x[2 * i + 1]);
+            f[4 * r + 2] = ex / (1.0 + fabs(ex));
+            f[4 * r + 3] = ey / (1.0 + fabs(ey));
+        }
+    }
+}
+
+static double gelu(double t) { return 0.5 * t * (1.0 + erf(t / sqrt(2.0))); }
+
+/* w: W1[128][64], b1[128], W2[128][128], b2[128], w3[128], b3 (row-major). */
+void oracle_init_mlp(int n, const double *feat, const double *w, double *p_out)
+{
+    const double *W1 = w, *b1 = W1 + OR_NH * OR_NF, *W2 = b1 + OR_NH;
+    const double *b2 = W2 + OR_NH * OR_NH, *w3 = b2 + OR_NH, *b3 = w3 + OR_NH;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        const double *f = feat + (size_t)i * OR_NF;
+        double h1[OR_NH], h2[OR_NH];
+        for (int o = 0; o < OR_NH; ++o) {
+            double a = b1[o];
+            for (int k = 0; k < OR_NF; ++k) a += W1[o * OR_NF + k] * f[k];
+            h1[o] = gelu(a);
+        }
+        for (int o = 0; o < OR_NH; ++o) {
+            double a = b2[o];
+            for (int k = 0; k < OR_NH; ++k) a += W2[o * OR_NH + k] * h1[k];
+            h2[o] = gelu(a);
+        }
+        double z = b3[0];
+        for (int k = 0; k < OR_NH; ++k) z += w3[k] * h2[k];
+        p_out[i] = 1.0 / (1.0 + exp(-z));
+    }
 }

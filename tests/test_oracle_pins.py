@@ -607,3 +607,74 @@ def test_track_nodes_no_inliers_is_reported():
                                         np.zeros(3, np.uint8), 1e-3, 1e-3, [[1.0, 2.0]],
                                         [1.0], [[1.0, 0, 0, 0]], [0.0])
     assert rc == O.ENOINLIERS and np.isnan(pos).all() and np.isnan(sig2).all()
+
+
+# ------------------------------------------------ learned EM start ---------
+
+def test_init_features_neighbours_match_kdtree_and_invariances():
+    from scipy.spatial import cKDTree
+    P = synth.gen_config(1, 2, with_frame=False)
+    a = O.alpha(320, 240)
+    F = O.init_features(P.src, P.dst, a)
+    assert F.shape == (200, 64)
+    x = P.src.astype(np.float64)
+    # the neighbour offsets are those of the 16 nearest other matches, in order
+    _, idx = cKDTree(x).query(x, k=17)
+    g = np.sqrt(a)
+    for i in range(200):
+        nb = [j for j in idx[i] if j != i][:16]
+        assert np.allclose(F[i, 0::4], g * (x[nb, 0] - x[i, 0]), atol=1e-12)
+        assert np.allclose(F[i, 1::4], g * (x[nb, 1] - x[i, 1]), atol=1e-12)
+    assert np.all(np.abs(F[:, 2::4]) < 1) and np.all(np.abs(F[:, 3::4]) < 1)
+    # a common shift of both frames, or a common extra displacement, changes nothing
+    s64, d64 = P.src.astype(np.float64), P.dst.astype(np.float64)   # shifts stay exact
+    F2 = O.init_features(s64 + 37.0, d64 + 37.0, a)
+    F3 = O.init_features(s64, d64 + 5.0, a)
+    assert np.allclose(F2, F, atol=1e-9) and np.allclose(F3, F, atol=1e-9)
+
+
+def test_init_features_ties_and_tiny_sets():
+    """Equal distances are ordered by index; with fewer than 16 other
+    matches the missing neighbours give zero features."""
+    src = np.array([[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1]], np.float32)
+    F = O.init_features(src, src, 1.0)
+    # match 0: all four others at distance 1, in index order 1, 2, 3, 4
+    assert np.allclose(F[0, 0:16:4], [1, -1, 0, 0]) and np.allclose(F[0, 1:16:4], [0, 0, 1, -1])
+    assert not F[0, 16:].any()
+
+
+def test_init_mlp_matches_torch_float64():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(8)
+    w = rng.normal(0, 0.3, O.N_WEIGHTS)
+    f = rng.normal(0, 1, (50, 64))
+    got = O.init_mlp(f, w)
+    nh, nf = O.N_HIDDEN, O.N_FEAT
+    k = 0
+    def take(m):
+        nonlocal k
+        out = torch.from_numpy(w[k:k + m].copy())
+        k += m
+        return out
+    W1 = take(nh * nf).reshape(nh, nf); b1 = take(nh)
+    W2 = take(nh * nh).reshape(nh, nh); b2 = take(nh)
+    w3 = take(nh); b3 = take(1)
+    t = torch.from_numpy(f)
+    h = torch.nn.functional.gelu(t @ W1.T + b1)
+    h = torch.nn.functional.gelu(h @ W2.T + b2)
+    want = torch.sigmoid(h @ w3 + b3).numpy()
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-14)
+
+
+def test_fit_from_start_points():
+    """p = 1 as an explicit start is the plain fit bit for bit; the
+    generator's labels as a start reach the plain fit's mask; a non-finite
+    start is rejected."""
+    P = synth.gen_config(1, 1, with_frame=False)
+    plain = O.fit(P.src, P.dst, 320, 240)
+    ones = O.fit(P.src, P.dst, 320, 240, init_p=np.ones(200))
+    assert ones.iters == plain.iters and np.array_equal(ones.p, plain.p)
+    lab = O.fit(P.src, P.dst, 320, 240, init_p=np.where(P.inlier, 0.99, 0.01))
+    assert np.array_equal(lab.mask, plain.mask) and lab.iters <= plain.iters
+    bad = O.fit(P.src, P.dst, 320, 240, init_p=np.full(200, np.nan))
+    assert bad.status == O.EINVAL
