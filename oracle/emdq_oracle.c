@@ -323,11 +323,11 @@ int oracle_fit_init(int n, const double *x, const double *y, int frame_w, int fr
         p[i] = init_p ? init_p[i] : 1.0;
         mask[i] = ((float)p[i] > (float)prm.p_thresh) ? 1 : 0;
     }
-    if (init_p && !all_finite(n, init_p)) {
+    if (init_p && !all_finite(n, init_p)) {   /* a non-finite input, like a coordinate */
         free(e2);
         free(pn);
         free(prev);
-        return OR_EINVAL;
+        return OR_ENONFINITE;
     }
     int k = 0, converged = 0, status = OR_OK;
     double sigma2 = 0.0, gamma = 0.0;

@@ -669,7 +669,7 @@ def test_init_mlp_matches_torch_float64():
 def test_fit_from_start_points():
     """p = 1 as an explicit start is the plain fit bit for bit; the
     generator's labels as a start reach the plain fit's mask; a non-finite
-    start is rejected."""
+    start is reported as a non-finite input."""
     P = synth.gen_config(1, 1, with_frame=False)
     plain = O.fit(P.src, P.dst, 320, 240)
     ones = O.fit(P.src, P.dst, 320, 240, init_p=np.ones(200))
@@ -677,4 +677,4 @@ def test_fit_from_start_points():
     lab = O.fit(P.src, P.dst, 320, 240, init_p=np.where(P.inlier, 0.99, 0.01))
     assert np.array_equal(lab.mask, plain.mask) and lab.iters <= plain.iters
     bad = O.fit(P.src, P.dst, 320, 240, init_p=np.full(200, np.nan))
-    assert bad.status == O.EINVAL
+    assert bad.status == O.ENONFINITE
