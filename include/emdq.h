@@ -117,6 +117,31 @@ emdq_status emdq_fit(emdq_model m, const float *src_xy, const float *dst_xy, int
                      int frame_w, int frame_h, const emdq_params *params,
                      hipStream_t stream);
 
+/* EMDQ fit started from given posteriors instead of p = 1: as emdq_fit, with
+ *   init_p  device float[n], the starting posterior of every match (the
+ *           starting mask is init_p > p_thresh).
+ * A non-finite init_p is reported by emdq_model_status as ENONFINITE.
+ * EINVAL also on a null init_p. */
+emdq_status emdq_fit_from(emdq_model m, const float *src_xy, const float *dst_xy, int n,
+                          int frame_w, int frame_h, const emdq_params *params,
+                          const float *init_p, hipStream_t stream);
+
+/* Learned EM start (not in the paper; an optional way to seed emdq_fit_from):
+ * for every match i, the 16 nearest other matches by source distance
+ * (ordered by squared distance in FP64, then index) give 64 features, per
+ * neighbour j:  g (x_j - x_i)  and  ss((d_j - d_i) / 8),  g = sqrt(alpha)
+ * (alpha as in emdq_fit for this frame size and params), d = dst - src,
+ * ss(t) = t / (1 + |t|);  a network  p = sigmoid(w3 . gelu(W2 gelu(W1 f + b1)
+ * + b2) + b3)  with 128-wide GELU layers maps them to a starting posterior.
+ *   weights  device float[24961]: W1[128][64], b1[128], W2[128][128], b2[128],
+ *            w3[128], b3 (row-major), e.g. the trained start_mlp.npy
+ *   p_out    device float[n]
+ * Needs no model.  EINVAL on null pointers, bad sizes or params; ETOOFEW
+ * for n < 2. */
+emdq_status emdq_learned_start(const float *src_xy, const float *dst_xy, int n, int frame_w,
+                               int frame_h, const emdq_params *params, const float *weights,
+                               float *p_out, hipStream_t stream);
+
 /* Loads per-node warp functions directly (Eq. (1) per node, as the SLAM
  * nodes of Sec. III carry them) instead of fitting: host arrays
  *   x_xy float[n][2] node positions at time 0, scale float[n],
@@ -153,6 +178,109 @@ emdq_status emdq_warp(emdq_model m, const uint8_t *frame_rgb, int fw, int fh,
                       int frame_pitch_bytes, float *canvas, int cw, int ch,
                       int canvas_pitch_px, int ox, int oy, int zx0, int zy0, int w, int h,
                       hipStream_t stream);
+
+/* Uncertainty of the field (Eq. (8)) at the grid points z = (zx0 + i,
+ * zy0 + k), 0 <= i < w, 0 <= k < h: min over the inliers j of
+ * exp(beta |z - x_j|^2).  beta is the already-scaled coefficient (Sec.
+ * III-G: 3e-3 / s^2 with s as for alpha).
+ *   out  device float[h][w]; +inf where the value exceeds the FP32 range,
+ *        NaN after a failed fit.
+ * EINVAL on a null model/output, w or h < 0, or beta not finite and > 0
+ * (w or h == 0 is a no-op). */
+emdq_status emdq_uncertainty(emdq_model m, float beta, int zx0, int zy0, int w, int h,
+                             float *out, hipStream_t stream);
+
+/* One tracking step of n_nodes deformation nodes on the current model (Sec.
+ * III-C, III-E; App. A).  For node i at position pos_xy[i] in the frame of
+ * the model's src points (its position at the previous frame):
+ *   (ds, dq) = blended scale and DQ at pos_xy[i] (Eqs. (2)-(3)), normalised;
+ *   scale[i], q[i] <- the App. A update of the node's warp function by
+ *                     (ds, dq), so that the new warp of the node's time-0
+ *                     position equals ds dq applied to its old image;
+ *   sigma2[i] <- ds^2 sigma2[i] + min_j exp(beta d_ij^2)  (Eqs. (8), (9));
+ *   pos_xy[i] <- ds dq(pos_xy[i])                          (Eq. (1)).
+ * All arrays are device memory, updated in place: pos_xy float[n][2]
+ * (8-byte aligned), scale float[n], q float[n][4] planar DQs (16-byte
+ * aligned; returned with unit real part and q_c >= 0), sigma2 float[n].
+ * A node where no inlier carries weight, or every node after a failed fit,
+ * gets NaN.  EINVAL on null arguments, n_nodes < 0, misalignment or beta
+ * not finite and > 0 (n_nodes == 0 is a no-op). */
+emdq_status emdq_track_nodes(emdq_model m, float beta, int n_nodes, float *pos_xy,
+                             float *scale, float *q, float *sigma2, hipStream_t stream);
+
+/* Arithmetic of the dense blend in emdq_field / emdq_warp (Eqs. (2)-(4)).
+ *   F32   the two factors of each weight and the node values in FP32 on FP32
+ *         MFMA (the default);
+ *   F16   both GEMM operands (per-axis Gaussian factors, and factor x node
+ *         value) rounded to FP16, FP32 accumulation; the node DQs and scales
+ *         are first re-expressed relative to a reference motion at each
+ *         64 x 128 pixel tile (exact algebra: the blend is linear in the DQ
+ *         and the DQ product bilinear), so the rounded values are small
+ *         deviations, and the epilogue (normalisation, Eq. (1)) is FP32;
+ *   BF16  as F16 with BF16 operands (8-bit significand: about 8x the error).
+ * The fit is FP32 in every mode. */
+typedef enum {
+    EMDQ_PREC_F32 = 0,
+    EMDQ_PREC_F16 = 1,
+    EMDQ_PREC_BF16 = 2
+} emdq_precision;
+
+/* Selects the arithmetic of later emdq_field / emdq_warp calls on this
+ * model (host-side setting, nothing is enqueued).  EINVAL on a null model
+ * or an unknown value. */
+emdq_status emdq_model_set_precision(emdq_model m, emdq_precision precision);
+
+/* ------------------------------------------------------------ batches ---
+ * Many independent frame pairs, each with its own model, processed with one
+ * launch per phase instead of one per pair and phase: the EM phases of all
+ * pairs run side by side, and the field / warp of all pairs is one flat
+ * launch over their tiles.  Results are read per model (emdq_model_status,
+ * emdq_model_results) and are bit-identical to the single-pair calls.  A
+ * batch object holds only the job tables (device) and a few pinned staging
+ * buffers; like a model, it is used from one stream at a time. */
+typedef struct emdq_batch_s *emdq_batch;
+
+/* Grid rectangle of one pair for emdq_batch_field / emdq_batch_warp; the
+ * fields mean what the arguments of emdq_field / emdq_warp of the same names
+ * mean.  out_xy is used by emdq_batch_field only; frame_rgb .. oy by
+ * emdq_batch_warp only. */
+typedef struct {
+    int zx0, zy0, w, h;
+    float *out_xy;
+    const uint8_t *frame_rgb;
+    int fw, fh, frame_pitch_bytes;
+    float *canvas;
+    int cw, ch, canvas_pitch_px, ox, oy;
+} emdq_region;
+
+/* Allocates job tables for up to max_pairs pairs (1 .. 65535). */
+emdq_status emdq_batch_create(int max_pairs, emdq_batch *out);
+
+/* Waits for the batch's last uploads and releases it.  Null is ignored. */
+void emdq_batch_free(emdq_batch b);
+
+/* emdq_fit of n_pairs pairs at once (host arrays of n_pairs entries):
+ * pair i fits n[i] matches src_xy[i] -> dst_xy[i] (device float[n[i]][2])
+ * of a frame_w[i] x frame_h[i] frame into models[i], with one params for
+ * all (null: defaults).  The models must be distinct.  Synchronises the
+ * stream a few times to read the EM stop flags of all pairs.  EINVAL /
+ * ETOOFEW as for emdq_fit (any pair), EHIP; per-pair outcomes are read with
+ * emdq_model_status. */
+emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
+                           const float *const *src_xy, const float *const *dst_xy,
+                           const int *n, const int *frame_w, const int *frame_h,
+                           const emdq_params *params, hipStream_t stream);
+
+/* emdq_field of every pair (FP32 blend) in one launch: models[i] over
+ * regions[i] (host array).  EINVAL as for emdq_field on any region. */
+emdq_status emdq_batch_field(emdq_batch b, int n_pairs, const emdq_model *models,
+                             const emdq_region *regions, hipStream_t stream);
+
+/* emdq_warp of every pair (FP32 blend) in one launch.  The pairs' target
+ * rectangles must not overlap in canvas memory: they are merged
+ * concurrently.  EINVAL as for emdq_warp on any region. */
+emdq_status emdq_batch_warp(emdq_batch b, int n_pairs, const emdq_model *models,
+                            const emdq_region *regions, hipStream_t stream);
 
 /* Waits for `stream` and returns the outcome of the last fit or
  * set_nodes: OK, WARN_NOT_CONVERGED, ENONFINITE, ENOINLIERS. */

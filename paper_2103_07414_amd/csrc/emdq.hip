@@ -11,9 +11,9 @@
 //                      weights exp(-alpha d^2) p_j (Eq. (4)); one wavefront per
 //                      match, lanes stride the other matches, two-pass
 //                      centred FP32 moments, FP64 re-fit of near-degenerate rows
-//   k_estep            DQ blend at every match (Eqs. (2)-(3)), residuals; the
-//                      last workgroup reduces (FP64, fixed order), updates the
-//                      posteriors, the inlier mask and the stop flag
+//   k_estep            DQ blend at every match (Eqs. (2)-(3)), residuals
+//   k_posterior        one workgroup: FP64 fixed-order reduction, posteriors,
+//                      inlier mask and the stop flag
 //   k_compact          packs the inliers for the field kernel (one workgroup,
 //                      ordered scan)
 //   k_field<MODE>      the W(P x N_in) . Q(N_in x 6) blend on FP32 MFMA, with
@@ -41,11 +41,12 @@ constexpr int kEChunk = 1024;           // matches (+ fits) staged per E-step sw
 constexpr int kCompactThreads = 1024;
 constexpr int kFieldThreads = 256;      // 4 wavefronts per workgroup
 constexpr int kTile = 32;               // 32 x 32 pixels per MFMA output tile
+constexpr int kBufferFlags = 0x00020000;   // raw buffer resource word 3 (gfx9 family)
 #ifndef EMDQ_RING
 #define EMDQ_RING 4
 #endif
 #ifndef EMDQ_SCHED_MASK
-#define EMDQ_SCHED_MASK 0x000F   // ALU, VALU, SALU, MFMA may cross
+#define EMDQ_SCHED_MASK 0   // nothing crosses (measured faster than letting ALU cross)
 #endif
 #ifndef EMDQ_SPLITK
 #define EMDQ_SPLITK 4
@@ -62,7 +63,6 @@ struct DevState {
     int iter;        // EM iterations done
     int done;        // 1 once the stop rule fired
     int n_in;        // number of packed inliers
-    unsigned ticket; // arrival counter of the E-step workgroups
     int changed;     // mask changed in the last iteration
     float sigma2;
     float gamma;
@@ -89,25 +89,26 @@ __device__ __forceinline__ bool finite2(float2 v) {
 
 // ------------------------------------------------------ state, loading ----
 
+__device__ __forceinline__ void reset_state(DevState *st) {
+    st->status = 0;
+    st->iter = 0;
+    st->done = 0;
+    st->n_in = 0;
+    st->changed = 0;
+    st->sigma2 = 0.f;
+    st->gamma = 0.f;
+}
+
 __global__ void k_reset(DevState *st) {
-    if (threadIdx.x == 0) {
-        st->status = 0;
-        st->iter = 0;
-        st->done = 0;
-        st->n_in = 0;
-        st->ticket = 0u;
-        st->changed = 0;
-        st->sigma2 = 0.f;
-        st->gamma = 0.f;
-    }
+    if (threadIdx.x == 0) reset_state(st);
 }
 
 // xy[i] = (src_i, dst_i); p = 1, mask = 1; a non-finite coordinate sets the
 // status to ENONFINITE (every writer stores the same value).
-__global__ void k_load(const float2 *__restrict__ src, const float2 *__restrict__ dst, int n,
+__device__ __forceinline__ void load_body(const float2 *__restrict__ src, const float2 *__restrict__ dst, int n,
                        float4 *__restrict__ xy, float *__restrict__ p,
-                       uint8_t *__restrict__ mask, DevState *st) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+                       uint8_t *__restrict__ mask, DevState *st, int block) {
+    int i = block * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float2 a = src[i], b = dst[i];
     xy[i] = make_float4(a.x, a.y, b.x, b.y);
@@ -117,6 +118,12 @@ __global__ void k_load(const float2 *__restrict__ src, const float2 *__restrict_
         atomicMin(&st->status, (int)EMDQ_ENONFINITE);
         atomicExch(&st->done, 1);
     }
+}
+
+__global__ void k_load(const float2 *__restrict__ src, const float2 *__restrict__ dst, int n,
+                       float4 *__restrict__ xy, float *__restrict__ p,
+                       uint8_t *__restrict__ mask, DevState *st) {
+    load_body(src, dst, n, xy, p, mask, st, blockIdx.x);
 }
 
 // ------------------------------------------------- blend evaluation ----
@@ -228,24 +235,33 @@ __device__ void fit_row_f64(int i, const float4 *__restrict__ xy, const float *_
 // centroids, relative to (x_i, y_i).  Pass 2 (weights recomputed): centred
 // cross-covariance terms and spreads, so no moment is formed by cancellation.
 // Then the closed-form 2D Procrustes fit.
-__global__ __launch_bounds__(kEmThreads) void k_mstep(
+__device__ __forceinline__ void mstep_body(
     const float4 *__restrict__ xy, const float *__restrict__ p, int n, float nal2,
     double alpha, float4 *__restrict__ q_out, float *__restrict__ s_out,
-    const DevState *__restrict__ st, int final_pass) {
+    const DevState *__restrict__ st, int final_pass, int block) {
     __shared__ float4 s_xy[kMChunk];
     __shared__ float s_p[kMChunk];
     if (st->status < 0) return;
     if (!final_pass && st->done) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int i = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
+    const int i = block * kRowsPerBlock + (threadIdx.x >> 6);
     const bool active = i < n;
     const float4 me = active ? xy[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const bool resident = n <= kMChunk;   // one staging serves both passes
     auto stage = [&](int c0, int cn) {
+        constexpr int kPer = kMChunk / kEmThreads;
+        float4 v[kPer];
+        float pv[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int t = threadIdx.x + k * kEmThreads;
+            if (t < cn) { v[k] = xy[c0 + t]; pv[k] = p[c0 + t]; }
+        }
         __syncthreads();
-        for (int t = threadIdx.x; t < cn; t += kEmThreads) {
-            s_xy[t] = xy[c0 + t];
-            s_p[t] = p[c0 + t];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int t = threadIdx.x + k * kEmThreads;
+            if (t < cn) { s_xy[t] = v[k]; s_p[t] = pv[k]; }
         }
         __syncthreads();
     };
@@ -255,17 +271,27 @@ __global__ __launch_bounds__(kEmThreads) void k_mstep(
         const int cn = min(kMChunk, n - c0);
         stage(c0, cn);
         if (active) {
-#pragma unroll 4
-            for (int t = lane; t < cn; t += kWave) {
-                const float4 v = s_xy[t];
+            auto acc1 = [&](const float4 &v, float pj) {
                 const float dxx = v.x - me.x, dxy = v.y - me.y;   // x_j - x_i
-                const float w = fast_exp2(nal2 * (dxx * dxx + dxy * dxy)) * s_p[t];
+                const float w = fast_exp2(nal2 * (dxx * dxx + dxy * dxy)) * pj;
                 S += w;
                 Ax += w * dxx;
                 Ay += w * dxy;
                 Bx += w * (v.z - me.z);                          // y_j - y_i
                 By += w * (v.w - me.w);
+            };
+            int t = lane;
+            for (; t + 3 * kWave < cn; t += 4 * kWave) {   // 4 LDS reads in flight
+                const float4 v0 = s_xy[t], v1 = s_xy[t + kWave], v2 = s_xy[t + 2 * kWave],
+                             v3 = s_xy[t + 3 * kWave];
+                const float p0 = s_p[t], p1 = s_p[t + kWave], p2 = s_p[t + 2 * kWave],
+                            p3 = s_p[t + 3 * kWave];
+                acc1(v0, p0);
+                acc1(v1, p1);
+                acc1(v2, p2);
+                acc1(v3, p3);
             }
+            for (; t < cn; t += kWave) acc1(s_xy[t], s_p[t]);
         }
     }
     S = wave_sum(S);
@@ -286,18 +312,28 @@ __global__ __launch_bounds__(kEmThreads) void k_mstep(
         const int cn = min(kMChunk, n - c0);
         if (!resident) stage(c0, cn);
         if (active && have_w) {
-#pragma unroll 4
-            for (int t = lane; t < cn; t += kWave) {
-                const float4 v = s_xy[t];
+            auto acc2 = [&](const float4 &v, float pj) {
                 const float dxx = v.x - me.x, dxy = v.y - me.y;
-                const float w = fast_exp2(nal2 * (dxx * dxx + dxy * dxy)) * s_p[t];
+                const float w = fast_exp2(nal2 * (dxx * dxx + dxy * dxy)) * pj;
                 const float ax = v.x - cxx, ay = v.y - cxy;    // x_j - xbar
                 const float bx = v.z - cyx, by = v.w - cyy;    // y_j - ybar
                 vx += w * (ax * ax + ay * ay);
                 vy += w * (bx * bx + by * by);
                 a += w * (bx * ax + by * ay);                  // C00 + C11
                 b += w * (by * ax - bx * ay);                  // C10 - C01
+            };
+            int t = lane;
+            for (; t + 3 * kWave < cn; t += 4 * kWave) {
+                const float4 v0 = s_xy[t], v1 = s_xy[t + kWave], v2 = s_xy[t + 2 * kWave],
+                             v3 = s_xy[t + 3 * kWave];
+                const float p0 = s_p[t], p1 = s_p[t + kWave], p2 = s_p[t + 2 * kWave],
+                            p3 = s_p[t + 3 * kWave];
+                acc2(v0, p0);
+                acc2(v1, p1);
+                acc2(v2, p2);
+                acc2(v3, p3);
             }
+            for (; t < cn; t += kWave) acc2(s_xy[t], s_p[t]);
         }
     }
     if (!active) return;
@@ -339,50 +375,74 @@ __global__ __launch_bounds__(kEmThreads) void k_mstep(
     }
 }
 
+__global__ __launch_bounds__(kEmThreads) void k_mstep(
+    const float4 *__restrict__ xy, const float *__restrict__ p, int n, float nal2,
+    double alpha, float4 *__restrict__ q_out, float *__restrict__ s_out,
+    const DevState *__restrict__ st, int final_pass) {
+    mstep_body(xy, p, n, nal2, alpha, q_out, s_out, st, final_pass, blockIdx.x);
+}
+
 // --------------------------------------------------------------- E-step ----
 
 // Blend of all fits at match i with weights exp(-alpha d^2) p_j (Eqs. (2)-(3)),
 // normalisation, prediction y_hat = s (R x_i + t) (Eq. (1)), residual e_i^2.
-// The last workgroup to finish turns the residuals into sigma^2, gamma, new
-// posteriors, the mask and the stop decision.
-__global__ __launch_bounds__(kEmThreads) void k_estep(
-    const float4 *__restrict__ xy, float *__restrict__ p, const float4 *__restrict__ q,
-    const float *__restrict__ s, int n, float nal2, double u, double sigma2_min,
-    double gamma_min, double gamma_max, float p_thresh, int max_iter,
-    float *__restrict__ e2, uint8_t *__restrict__ mask, DevState *st) {
+__device__ __forceinline__ void estep_body(
+    const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
+    const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
+    const DevState *__restrict__ st, int block) {
     __shared__ float4 s_xy[kEChunk];
     __shared__ float4 s_q[kEChunk];
     __shared__ float2 s_ps[kEChunk];   // (p_j, s_j - 1)
     if (st->status < 0 || st->done) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int i = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
+    const int i = block * kRowsPerBlock + (threadIdx.x >> 6);
     const bool active = i < n;
     const float4 me = active ? xy[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     float W = 0.f, Gd = 0.f, Cd = 0.f, Sn = 0.f, X = 0.f, Y = 0.f;
     for (int c0 = 0; c0 < n; c0 += kEChunk) {
         const int cn = min(kEChunk, n - c0);
-        __syncthreads();
-        for (int t = threadIdx.x; t < cn; t += kEmThreads) {
-            s_xy[t] = xy[c0 + t];
-            s_q[t] = q[c0 + t];
-            s_ps[t] = make_float2(p[c0 + t], s[c0 + t] - 1.f);
+        {
+            constexpr int kPer = kEChunk / kEmThreads;
+            float4 v[kPer], qv[kPer];
+            float pv[kPer], sv[kPer];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int t = threadIdx.x + k * kEmThreads;
+                if (t < cn) { v[k] = xy[c0 + t]; qv[k] = q[c0 + t]; pv[k] = p[c0 + t]; sv[k] = s[c0 + t]; }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int t = threadIdx.x + k * kEmThreads;
+                if (t < cn) { s_xy[t] = v[k]; s_q[t] = qv[k]; s_ps[t] = make_float2(pv[k], sv[k] - 1.f); }
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (active) {
-#pragma unroll 4
-            for (int t = lane; t < cn; t += kWave) {
-                const float4 v = s_xy[t];
-                const float2 ps = s_ps[t];
+            auto acc1 = [&](const float4 &v, const float2 &ps, const float4 &qj) {
                 const float dx = v.x - me.x, dy = v.y - me.y;
                 const float w = fast_exp2(nal2 * (dx * dx + dy * dy)) * ps.x;
-                const float4 qj = s_q[t];
                 W += w;
                 Gd += w * ps.y;
                 Cd += w * (qj.x - 1.f);
                 Sn += w * qj.y;
                 X += w * qj.z;
                 Y += w * qj.w;
+            };
+            int t = lane;
+            for (; t + 3 * kWave < cn; t += 4 * kWave) {   // 4 LDS reads in flight
+                const float4 v0 = s_xy[t], v1 = s_xy[t + kWave], v2 = s_xy[t + 2 * kWave],
+                             v3 = s_xy[t + 3 * kWave];
+                const float2 a0 = s_ps[t], a1 = s_ps[t + kWave], a2 = s_ps[t + 2 * kWave],
+                             a3 = s_ps[t + 3 * kWave];
+                const float4 q0 = s_q[t], q1 = s_q[t + kWave], q2 = s_q[t + 2 * kWave],
+                             q3 = s_q[t + 3 * kWave];
+                acc1(v0, a0, q0);
+                acc1(v1, a1, q1);
+                acc1(v2, a2, q2);
+                acc1(v3, a3, q3);
             }
+            for (; t < cn; t += kWave) acc1(s_xy[t], s_ps[t], s_q[t]);
         }
     }
     if (active) {
@@ -401,33 +461,39 @@ __global__ __launch_bounds__(kEmThreads) void k_estep(
         }
         if (lane == 0) e2[i] = err;
     }
+}
 
-    // ---- arrival: the last workgroup finishes the iteration
-    __shared__ int last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned t = atomicAdd(&st->ticket, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+__global__ __launch_bounds__(kEmThreads) void k_estep(
+    const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
+    const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
+    const DevState *__restrict__ st) {
+    estep_body(xy, p, q, s, n, nal2, e2, st, blockIdx.x);
+}
 
-    __shared__ double red_p[kEmThreads], red_pe[kEmThreads];
+// Finishes an EM iteration (one workgroup): p-weighted sums of the residuals
+// (FP64, fixed order), sigma^2 and gamma, new posteriors (FP64), the inlier
+// mask and the stop rule.  A kernel of its own, so the residuals of all
+// matches are visible without any cross-workgroup fence.
+constexpr int kPostThreads = 1024;
+
+__device__ __forceinline__ void posterior_body(
+    float *__restrict__ p, const float *__restrict__ e2, uint8_t *__restrict__ mask, int n,
+    double u, double sigma2_min, double gamma_min, double gamma_max, float p_thresh,
+    int max_iter, DevState *st, int block) {
+    if (st->status < 0 || st->done) return;
+    __shared__ double red_p[kPostThreads], red_pe[kPostThreads];
     __shared__ int any_changed;
     if (threadIdx.x == 0) any_changed = 0;
     double sp = 0.0, spe = 0.0;
-    for (int r = threadIdx.x; r < n; r += kEmThreads) {
+    for (int r = threadIdx.x; r < n; r += kPostThreads) {
         const double pr = (double)p[r];
-        const float er = __hip_atomic_load(&e2[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         sp += pr;
-        if (pr > 0.0) spe += pr * (double)er;
+        if (pr > 0.0) spe += pr * (double)e2[r];
     }
     red_p[threadIdx.x] = sp;
     red_pe[threadIdx.x] = spe;
     __syncthreads();
-    for (int off = kEmThreads / 2; off >= 1; off >>= 1) {
+    for (int off = kPostThreads / 2; off >= 1; off >>= 1) {
         if (threadIdx.x < off) {
             red_p[threadIdx.x] += red_p[threadIdx.x + off];
             red_pe[threadIdx.x] += red_pe[threadIdx.x + off];
@@ -439,7 +505,6 @@ __global__ __launch_bounds__(kEmThreads) void k_estep(
         if (threadIdx.x == 0) {
             st->status = EMDQ_ENOINLIERS;
             st->done = 1;
-            st->ticket = 0u;
         }
         return;
     }
@@ -447,15 +512,12 @@ __global__ __launch_bounds__(kEmThreads) void k_estep(
     if (!(sigma2 >= sigma2_min)) sigma2 = sigma2_min;
     double gamma = SP / (double)n;
     gamma = gamma < gamma_min ? gamma_min : (gamma > gamma_max ? gamma_max : gamma);
-    const double two_pi = 6.283185307179586;
     const double inv2s = 1.0 / (2.0 * sigma2);
-    const double norm = 1.0 / (two_pi * sigma2);
+    const double norm = 1.0 / (6.283185307179586 * sigma2);
     const double b = (1.0 - gamma) * u;
     int changed = 0;
-    __syncthreads();
-    for (int r = threadIdx.x; r < n; r += kEmThreads) {
-        const float er = __hip_atomic_load(&e2[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double a = gamma * exp(-(double)er * inv2s) * norm;
+    for (int r = threadIdx.x; r < n; r += kPostThreads) {
+        const double a = gamma * exp(-(double)e2[r] * inv2s) * norm;
         const float pn = (float)(a / (a + b));
         p[r] = pn;
         const uint8_t m = pn > p_thresh ? 1 : 0;
@@ -476,9 +538,14 @@ __global__ __launch_bounds__(kEmThreads) void k_estep(
             st->done = 1;
             st->status = EMDQ_WARN_NOT_CONVERGED;
         }
-        st->ticket = 0u;
-        __threadfence();
     }
+}
+
+__global__ __launch_bounds__(kPostThreads) void k_posterior(
+    float *__restrict__ p, const float *__restrict__ e2, uint8_t *__restrict__ mask, int n,
+    double u, double sigma2_min, double gamma_min, double gamma_max, float p_thresh,
+    int max_iter, DevState *st) {
+    posterior_body(p, e2, mask, n, u, sigma2_min, gamma_min, gamma_max, p_thresh, max_iter, st, blockIdx.x);
 }
 
 // ------------------------------------------------------------ compaction ----
@@ -487,9 +554,10 @@ __global__ __launch_bounds__(kEmThreads) void k_estep(
 // packed[2k+1] = (q_x, q_y, s - 1, 1) (deviation-coded, see
 // blend_displacement).  One workgroup; each thread owns a
 // contiguous run of matches, runs are ordered by an exclusive scan.
-__global__ __launch_bounds__(kCompactThreads) void k_compact(
+__device__ __forceinline__ void compact_body(
     const float4 *__restrict__ xy, const float4 *__restrict__ q, const float *__restrict__ s,
-    const uint8_t *__restrict__ mask, int n, float4 *__restrict__ packed, DevState *st) {
+    const uint8_t *__restrict__ mask, int n, float4 *__restrict__ packed,
+    float *__restrict__ xs, float *__restrict__ ys, DevState *st, int block) {
     __shared__ int scan[kCompactThreads];
     if (st->status < 0) return;
     const int t = threadIdx.x;
@@ -511,6 +579,8 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(
         const float4 v = xy[i], qi = q[i];
         packed[2 * pos] = make_float4(v.x, v.y, qi.x - 1.f, qi.y);
         packed[2 * pos + 1] = make_float4(qi.z, qi.w, s[i] - 1.f, 1.f);
+        xs[pos] = v.x;
+        ys[pos] = v.y;
         ++pos;
     }
     if (t == kCompactThreads - 1) {
@@ -518,6 +588,13 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(
         st->n_in = total;
         if (total == 0) st->status = EMDQ_ENOINLIERS;
     }
+}
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact(
+    const float4 *__restrict__ xy, const float4 *__restrict__ q, const float *__restrict__ s,
+    const uint8_t *__restrict__ mask, int n, float4 *__restrict__ packed,
+    float *__restrict__ xs, float *__restrict__ ys, DevState *st) {
+    compact_body(xy, q, s, mask, n, packed, xs, ys, st, blockIdx.x);
 }
 
 // ------------------------------------------------------------ field / warp ----
@@ -536,25 +613,63 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(
 // SPLITK wavefronts share one tile and split the inliers; their partial sums
 // are added through LDS in a fixed order, and each then finishes 16 / SPLITK
 // of the tile's accumulator registers.
-template <int SPLITK>
+template <int SPLITK, int RB>
 struct FieldLds {
-    float part[SPLITK > 1 ? 4 : 1][SPLITK > 1 ? 6 * (16 - 16 / SPLITK) : 1][kWave];
+    float part[SPLITK > 1 ? 4 : 1][SPLITK > 1 ? RB * 6 * (16 - 16 / SPLITK) : 1][kWave];
 };
 
 enum { kModeField = 0, kModeWarp = 1 };
 
-template <int MODE, int SPLITK>
-__global__ __launch_bounds__(kFieldThreads) void k_field(
+// Sec. III-F, Eqs. (23)-(24): bilinear sample of the new frame at u = z + d
+// and running-average merge into canvas pixel z + (ox, oy); pixels whose u
+// leaves [0, fw-1] x [0, fh-1] are left unchanged.  With integer z the sample
+// cell and the bilinear weights come from d alone, so u is never rounded.
+__device__ __forceinline__ void warp_merge(int zx, int zy, float2 d,
+                                           const uint8_t *__restrict__ frame, int fw, int fh,
+                                           int fpitch, float4 *__restrict__ canvas, int cpitch,
+                                           int ox, int oy) {
+    const float fzx = (float)zx, fzy = (float)zy;
+    if (!(d.x >= -fzx && d.x <= (float)(fw - 1 - zx) && d.y >= -fzy &&
+          d.y <= (float)(fh - 1 - zy)))
+        return;
+    const float flx = floorf(d.x), fly = floorf(d.y);
+    const int x0 = zx + (int)flx, y0 = zy + (int)fly;
+    const int x1 = min(x0 + 1, fw - 1), y1 = min(y0 + 1, fh - 1);
+    const float ax = d.x - flx, by = d.y - fly;
+    const uint8_t *row0 = frame + (size_t)y0 * fpitch;
+    const uint8_t *row1 = frame + (size_t)y1 * fpitch;
+    const float w00 = (1.f - ax) * (1.f - by), w01 = ax * (1.f - by);
+    const float w10 = (1.f - ax) * by, w11 = ax * by;
+    float v[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+        v[ch] = w00 * (float)row0[3 * x0 + ch] + w01 * (float)row0[3 * x1 + ch] +
+                w10 * (float)row1[3 * x0 + ch] + w11 * (float)row1[3 * x1 + ch];
+    float4 *px = canvas + (size_t)(zy + oy) * cpitch + (zx + ox);
+    float4 cur = *px;
+    const float A = cur.w, A1 = A + 1.f;
+    cur.x = (A * cur.x + v[0]) / A1;
+    cur.y = (A * cur.y + v[1]) / A1;
+    cur.z = (A * cur.z + v[2]) / A1;
+    cur.w = fminf(A1, 30.f);
+    *px = cur;
+}
+
+// RB row blocks of 32 share the B operands: a wavefront's tile is 32 RB rows x
+// 32 columns and each pair of inliers costs RB + 1 exponentials and 6
+// multiplies for 6 RB MFMAs.
+template <int MODE, int SPLITK, int RB>
+__device__ __forceinline__ void field_body(
     const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
     int zy0, int w, int h, int tiles_x, int n_tiles, float2 *__restrict__ out,
     const uint8_t *__restrict__ frame, int fw, int fh, int fpitch, float4 *__restrict__ canvas,
-    int cpitch, int ox, int oy) {
+    int cpitch, int ox, int oy, int block) {
     constexpr int kTilesPerWg = 4 / SPLITK;
     constexpr int kRegsOwned = 16 / SPLITK;
-    __shared__ FieldLds<SPLITK> lds;
+    __shared__ FieldLds<SPLITK, RB> lds;
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-    const int tile = blockIdx.x * kTilesPerWg + wave / SPLITK;
+    const int tile = block * kTilesPerWg + wave / SPLITK;
     const int ks = wave % SPLITK;
     const int status = st->status;
     const int n_in = st->n_in;
@@ -562,83 +677,103 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(
     if (MODE == kModeWarp && bad) return;    // canvas left unchanged
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int px0 = zx0 + tx * kTile, py0 = zy0 + ty * kTile;
+    const int px0 = zx0 + tx * kTile, py0 = zy0 + ty * kTile * RB;
     const int col = lane & 31, half = lane >> 5;
     const float zcol = (float)(px0 + col);   // z_x of the B operand column
-    const float zrow = (float)(py0 + col);   // z_y of the A operand row
+    float zrow[RB];                          // z_y of the A operand rows
+#pragma unroll
+    for (int b = 0; b < RB; ++b) zrow[b] = (float)(py0 + kTile * b + col);
 
-    f32x16 acc[6];
+    f32x16 acc[RB][6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c)
+    for (int b = 0; b < RB; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[b][c][r] = 0.f;
 
     if (!bad && tile < n_tiles) {
-        // wavefront-uniform K range (scalar loop control)
-        const int kper = ((n_in + 2 * SPLITK - 1) / (2 * SPLITK)) * 2;   // even
+        // Wavefront-uniform K range: a whole number of ring groups, so the
+        // ranges of the SPLITK wavefronts never overlap; records past the
+        // inliers read as zero (buffer range check) and add nothing.  The
+        // buffer resource is rebuilt per step on the scalar unit, so record
+        // addressing costs no vector instruction.
+        constexpr int kGroup = 2 * kRing;
+        const int kper = ((n_in + SPLITK * kGroup - 1) / (SPLITK * kGroup)) * kGroup;
         const int kb = __builtin_amdgcn_readfirstlane(ks * kper);
-        const int ke = __builtin_amdgcn_readfirstlane(min(kb + kper, n_in));
+        const int kend = kb + kper;
+        const int voff = half * 32;        // lanes 32..63 take the odd inlier
+        auto load = [&](int j0, float4 &r0, float4 &r1) {
+            const int jj = __builtin_amdgcn_readfirstlane(min(j0, n_in));
+            const int bytes = __builtin_amdgcn_readfirstlane((n_in - jj) * 32);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(packed + 2 * jj), (short)0, bytes, kBufferFlags);
+            r0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0));
+            r1 = __builtin_bit_cast(float4,
+                                    __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16, 0, 0));
+        };
+        auto factors = [&](const float4 &r0, float (&a)[RB], float &g) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                const float dy = zrow[b] - r0.y;
+                a[b] = fast_exp2(nal2 * dy * dy);
+            }
+            const float dx = zcol - r0.x;
+            g = fast_exp2(nal2 * dx * dx);
+        };
         // Ring of kRing record buffers: step u of a group uses buffer u and
         // refills it for the same step of the next group, so every load has
-        // kRing K steps (kRing x 6 MFMAs) to land.  The Gaussian factors of
-        // step u + 1 are computed while the MFMAs of step u run.  The group
-        // loop is fully unrolled, so the buffers stay in fixed registers.
-        // Indices past the range are clamped to the last inlier and their
-        // weight is zero.
-        auto load = [&](int j0, float4 &r0, float4 &r1) {
-            const int jl = min(j0 + half, n_in - 1);
-            r0 = packed[2 * jl];
-            r1 = packed[2 * jl + 1];
-        };
-        auto factors = [&](int j0, const float4 &r0, float &a, float &g) {
-            const float dy = zrow - r0.y;
-            a = fast_exp2(nal2 * dy * dy);
-            const float dx = zcol - r0.x;
-            const float gv = fast_exp2(nal2 * dx * dx);
-            g = j0 + half < ke ? gv : 0.f;
-        };
+        // kRing K steps to land.  The Gaussian factors of step u + 1 are
+        // computed while the MFMAs of step u run.  The group loop is fully
+        // unrolled, so the buffers stay in fixed registers.
         float4 ra[kRing], rb[kRing];
 #pragma unroll
         for (int u = 0; u < kRing; ++u) {
             load(kb + 2 * u, ra[u], rb[u]);
             __builtin_amdgcn_sched_barrier(0);   // issue in ring order
         }
-        const int kend = kb + ((ke - kb + 2 * kRing - 1) / (2 * kRing)) * (2 * kRing);
-        float a, g;
-        factors(kb, ra[0], a, g);
+        float a[RB], g;
+        factors(ra[0], a, g);
         for (int j0 = kb; j0 < kend; j0 += 2 * kRing) {
 #pragma unroll
             for (int u = 0; u < kRing; ++u) {
                 const int j = j0 + 2 * u;
                 const float4 r0 = ra[u], r1 = rb[u];
-                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, g * r0.z, acc[0], 0, 0, 0);
-                float an, gn;   // next step (its record is already in the ring)
-                factors(j + 2, ra[(u + 1) % kRing], an, gn);
-                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, g * r0.w, acc[1], 0, 0, 0);
-                acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, g * r1.x, acc[2], 0, 0, 0);
-                acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, g * r1.y, acc[3], 0, 0, 0);
-                acc[4] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, g * r1.z, acc[4], 0, 0, 0);
-                acc[5] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, g * r1.w, acc[5], 0, 0, 0);
+                const float q[6] = {r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+                float an[RB], gn;   // next step (its record is already in the ring)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const float bop = g * q[c];
+#pragma unroll
+                    for (int bl = 0; bl < RB; ++bl)
+                        acc[bl][c] =
+                            __builtin_amdgcn_mfma_f32_32x32x2f32(a[bl], bop, acc[bl][c], 0, 0, 0);
+                    if (c == 0) factors(ra[(u + 1) % kRing], an, gn);
+                }
                 load(j + 2 * kRing, ra[u], rb[u]);
-                a = an;
+#pragma unroll
+                for (int bl = 0; bl < RB; ++bl) a[bl] = an[bl];
                 g = gn;
                 // memory operations keep their place (otherwise the loads
-                // sink to their use); arithmetic may move across
+                // sink to their use)
                 __builtin_amdgcn_sched_barrier(EMDQ_SCHED_MASK);
             }
         }
     }
 
     // ---- split-K reduction: wavefront ks keeps registers [ks*R, ks*R + R)
+    // of every row block
     const int rbase = ks * kRegsOwned;
     if constexpr (SPLITK > 1) {
-        // publish the registers other wavefronts own
         int slot = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             if (r >= rbase && r < rbase + kRegsOwned) continue;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) lds.part[wave][slot * 6 + c][lane] = acc[c][r];
+            for (int bl = 0; bl < RB; ++bl)
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    lds.part[wave][(slot * RB + bl) * 6 + c][lane] = acc[bl][c][r];
             ++slot;
         }
         __syncthreads();
@@ -648,72 +783,733 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(
         for (int rr = 0; rr < kRegsOwned; ++rr) {
             const int r = rbase + rr;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                float sum = 0.f;
-                for (int src = 0; src < SPLITK; ++src) {
-                    float v;
-                    if (src == ks) {
-                        v = acc[c][r];
-                    } else {
-                        // slot of register r in wavefront src's list
-                        const int src_base = src * kRegsOwned;
-                        const int sl = r < src_base ? r : r - kRegsOwned;
-                        v = lds.part[wbase + src][sl * 6 + c][lane];
+            for (int bl = 0; bl < RB; ++bl)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    float sum = 0.f;
+                    for (int src = 0; src < SPLITK; ++src) {
+                        float v;
+                        if (src == ks) {
+                            v = acc[bl][c][r];
+                        } else {
+                            // slot of register r in wavefront src's list
+                            const int src_base = src * kRegsOwned;
+                            const int sl = r < src_base ? r : r - kRegsOwned;
+                            v = lds.part[wbase + src][(sl * RB + bl) * 6 + c][lane];
+                        }
+                        sum = src == 0 ? v : sum + v;
                     }
-                    sum = src == 0 ? v : sum + v;
+                    acc[bl][c][r] = sum;
                 }
-                acc[c][r] = sum;
-            }
         }
     }
     if (tile >= n_tiles) return;
 
     // ---- epilogue: DQ normalisation, Eq. (1), then (warp) sample + merge
 #pragma unroll
+    for (int bl = 0; bl < RB; ++bl)
+#pragma unroll
     for (int rr = 0; rr < kRegsOwned; ++rr) {
         const int r = rbase + rr;
         const int zx = px0 + col;
-        const int zy = py0 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int zy = py0 + kTile * bl + 8 * (r >> 2) + 4 * half + (r & 3);
         if (zx >= zx0 + w || zy >= zy0 + h) continue;
         const float fzx = (float)zx, fzy = (float)zy;
-        const float2 d = blend_displacement(acc[5][r], acc[0][r], acc[1][r], acc[2][r],
-                                            acc[3][r], acc[4][r], fzx, fzy);
+        const float2 d = blend_displacement(acc[bl][5][r], acc[bl][0][r], acc[bl][1][r],
+                                            acc[bl][2][r], acc[bl][3][r], acc[bl][4][r], fzx, fzy);
         if constexpr (MODE == kModeField) {
             float2 o = bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
                            : make_float2(fzx + d.x, fzy + d.y);
             out[(size_t)(zy - zy0) * w + (zx - zx0)] = o;
         } else {
-            // u = z + d with integer z: the sample cell and the bilinear
-            // weights come from d alone, so u is never rounded
-            if (!(d.x >= -fzx && d.x <= (float)(fw - 1 - zx) && d.y >= -fzy &&
-                  d.y <= (float)(fh - 1 - zy)))
-                continue;
-            const float flx = floorf(d.x), fly = floorf(d.y);
-            const int x0 = zx + (int)flx, y0 = zy + (int)fly;
-            const int x1 = min(x0 + 1, fw - 1), y1 = min(y0 + 1, fh - 1);
-            const float a = d.x - flx, b = d.y - fly;
-            const uint8_t *row0 = frame + (size_t)y0 * fpitch;
-            const uint8_t *row1 = frame + (size_t)y1 * fpitch;
-            const float w00 = (1.f - a) * (1.f - b), w01 = a * (1.f - b);
-            const float w10 = (1.f - a) * b, w11 = a * b;
-            float v[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch)
-                v[ch] = w00 * (float)row0[3 * x0 + ch] + w01 * (float)row0[3 * x1 + ch] +
-                        w10 * (float)row1[3 * x0 + ch] + w11 * (float)row1[3 * x1 + ch];
-            float4 *px = canvas + (size_t)(zy + oy) * cpitch + (zx + ox);
-            float4 cur = *px;
-            const float A = cur.w, A1 = A + 1.f;
-            cur.x = (A * cur.x + v[0]) / A1;
-            cur.y = (A * cur.y + v[1]) / A1;
-            cur.z = (A * cur.z + v[2]) / A1;
-            cur.w = fminf(A1, 30.f);
-            *px = cur;
+            warp_merge(zx, zy, d, frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
         }
     }
 }
 
+template <int MODE, int SPLITK, int RB>
+__global__ __launch_bounds__(kFieldThreads) void k_field(
+    const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
+    int zy0, int w, int h, int tiles_x, int n_tiles, float2 *__restrict__ out,
+    const uint8_t *__restrict__ frame, int fw, int fh, int fpitch, float4 *__restrict__ canvas,
+    int cpitch, int ox, int oy) {
+    field_body<MODE, SPLITK, RB>(packed, st, nal2, zx0, zy0, w, h, tiles_x, n_tiles, out, frame, fw, fh, fpitch, canvas, cpitch, ox, oy, blockIdx.x);
+}
+
+// ------------------------------------------- half-precision field / warp ----
+//
+// The same blend with the two GEMM operands in FP16 or BF16 and FP32
+// accumulation (v_mfma_f32_32x32x16_{f16,bf16}: lane l holds A[l % 32][8 (l / 32)
+// + i] and B[8 (l / 32) + i][l % 32], i < 8; accumulator layout as above).
+//
+// Deviation coding per workgroup tile.  The blend is linear in the DQ
+// components and the DQ product is bilinear, so for fixed unit DQs a, b
+//   sum_j w_j (a q_j b) = a (sum_j w_j q_j) b,
+// and normalising by the norm of the real part commutes with both products.
+// Each workgroup takes a reference motion T0 = (R0, t0) and scale s0, the
+// blend at its tile centre p, and blends q'_j = a q_j b with b the
+// translation by p and a = R0^-1 composed with the translation by -c0,
+// c0 = T0(p): q'_j is the motion u -> R0^T (T_j(u + p) - c0), close to the
+// identity for the nodes that carry weight at the tile.  The stored values
+// (q'_c - 1, q'_s, q'_x, q'_y, s_j - s0) are then small, which is what keeps
+// the 11-bit (FP16) or 8-bit (BF16) operands accurate; the epilogue undoes
+// the coding exactly: T(z) = R0 T'(z - p) + c0, s = s0 + mean(s_j - s0).
+//
+// Workgroup tile 64 rows x 128 columns; wavefront w owns columns
+// [32 w, 32 w + 32) and both 32-row blocks, so each B operand (Gaussian x
+// factor times one coded component, built in registers) feeds two MFMAs.
+// The per-axis Gaussian factors of the next chunk of 64 inliers are computed
+// into LDS while the MFMAs of the current chunk run (double buffer, one
+// barrier per chunk).
+enum { kDtF16 = 0, kDtBF16 = 1 };
+constexpr int kHTx = 128, kHTy = 64, kHK = 64, kHStride = kHK + 8;   // LDS rows padded
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bhalf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bhalf4 __attribute__((ext_vector_type(4)));
+
+template <int DT> struct HalfT;
+template <> struct HalfT<kDtF16> {
+    using T = _Float16;
+    using V8 = half8;
+    using V4 = half4;
+    using Q = _Float16;   // coded node values in LDS
+};
+template <> struct HalfT<kDtBF16> {
+    using T = __bf16;
+    using V8 = bhalf8;
+    using V4 = bhalf4;
+    using Q = float;      // BF16 products are formed in FP32, then rounded
+};
+
+template <int DT>
+struct alignas(16) HalfLds {
+    typename HalfT<DT>::T gy[2][kHTy][kHStride];
+    typename HalfT<DT>::T gx[2][kHTx][kHStride];
+    typename HalfT<DT>::Q qd[2][5][kHK];
+    float red[4][8];
+};
+
+// Planar DQ product (c1 + s1 k + eps (x1 i + y1 j)) (c2 + s2 k + eps (x2 i +
+// y2 j)): the motion that applies the right operand first.
+__device__ __forceinline__ float4 dq_mul(float4 a, float4 b) {
+    return make_float4(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x,
+                       a.x * b.z - a.y * b.w + a.z * b.x + a.w * b.y,
+                       a.x * b.w + a.y * b.z + a.w * b.x - a.z * b.y);
+}
+
+template <int MODE, int DT>
+__global__ __launch_bounds__(kFieldThreads) void k_field_half(
+    const float4 *__restrict__ packed, const float *__restrict__ xs,
+    const float *__restrict__ ys, const DevState *__restrict__ st, float ka, int zx0, int zy0,
+    int w, int h, int tiles_x, float2 *__restrict__ out, const uint8_t *__restrict__ frame,
+    int fw, int fh, int fpitch, float4 *__restrict__ canvas, int cpitch, int ox, int oy) {
+    using T = typename HalfT<DT>::T;
+    using V8 = typename HalfT<DT>::V8;
+    using V4 = typename HalfT<DT>::V4;
+    __shared__ HalfLds<DT> L;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & (kWave - 1);
+    const int col = lane & 31, half = lane >> 5;
+    const int status = st->status;
+    const int n_in = st->n_in;
+    const bool bad = status < 0 || n_in <= 0;
+    if (MODE == kModeWarp && bad) return;
+
+    const int px0 = zx0 + (int)(blockIdx.x % tiles_x) * kHTx;
+    const int py0 = zy0 + (int)(blockIdx.x / tiles_x) * kHTy;
+    const float pcx = (float)px0 + 0.5f * (kHTx - 1), pcy = (float)py0 + 0.5f * (kHTy - 1);
+
+    // ---- reference at the tile centre: FP32 blend over all inliers
+    float sums[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (!bad) {
+        const float nal2 = -ka * ka;
+        for (int j = tid; j < n_in; j += kFieldThreads) {
+            const float4 r0 = packed[2 * j], r1 = packed[2 * j + 1];
+            const float dx = pcx - r0.x, dy = pcy - r0.y;
+            const float wj = fast_exp2(nal2 * (dx * dx + dy * dy));
+            sums[0] += wj;
+            sums[1] += wj * r0.z;
+            sums[2] += wj * r0.w;
+            sums[3] += wj * r1.x;
+            sums[4] += wj * r1.y;
+            sums[5] += wj * r1.z;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sums[c] = wave_sum(sums[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) L.red[wave][c] = sums[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sums[c] = ((L.red[0][c] + L.red[1][c]) + L.red[2][c]) + L.red[3][c];
+    float ch0 = 1.f, sh0 = 0.f, d0x = 0.f, d0y = 0.f, sm1 = 0.f;
+    {
+        const float W0 = sums[0];
+        const float C = 1.f + sums[1] / W0, S = sums[2] / W0;
+        const float X = sums[3] / W0, Y = sums[4] / W0;
+        const float in = 1.f / sqrtf(C * C + S * S);
+        const float c = C * in, sn = S * in, dx = X * in, dy = Y * in;
+        const float tx = 2.f * (c * dx - sn * dy), ty = 2.f * (sn * dx + c * dy);
+        // (R0 - I) p + t0, rounded to 1/64 px so that c0 = p + d0 is exact
+        const float ex = -2.f * sn * sn * pcx - 2.f * c * sn * pcy + tx;
+        const float ey = 2.f * c * sn * pcx - 2.f * sn * sn * pcy + ty;
+        const float gx = rintf(64.f * ex) * (1.f / 64.f), gy = rintf(64.f * ey) * (1.f / 64.f);
+        const float g = sums[5] / W0;
+        if (W0 > 0.f && __builtin_isfinite(c) && __builtin_isfinite(sn) &&
+            __builtin_isfinite(gx) && __builtin_isfinite(gy) && __builtin_isfinite(g)) {
+            ch0 = c;
+            sh0 = sn;
+            d0x = gx;
+            d0y = gy;
+            sm1 = g;
+        }
+    }
+    const float cos0 = ch0 * ch0 - sh0 * sh0, sin0 = 2.f * ch0 * sh0;
+    const float c0x = pcx + d0x, c0y = pcy + d0y;
+    // a = R0^-1 (translation by -c0);  b = translation by p
+    const float4 aq = make_float4(ch0, -sh0, -0.5f * (ch0 * c0x + sh0 * c0y),
+                                  -0.5f * (ch0 * c0y - sh0 * c0x));
+    const float4 bq = make_float4(1.f, 0.f, 0.5f * pcx, 0.5f * pcy);
+    const float ch0m1 = -sh0 * sh0 / (1.f + ch0);   // ch0 - 1 without cancellation
+
+    f32x16 acc[2][6];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[b][c][r] = 0.f;
+
+    if (!bad) {
+        const int nchunks = (n_in + kHK - 1) / kHK;
+        // generation roles: Gaussian x factor of column gcol for the 32
+        // inliers [32 (wave / 2), +32) of a chunk, y factor of row `lane` for
+        // the 16 inliers [16 wave, +16); wavefront 3 also codes the chunk's
+        // node values (one inlier per lane)
+        const int gcol = 64 * (wave & 1) + lane;
+        const float zxa = ka * (float)(px0 + gcol), zya = ka * (float)(py0 + lane);
+        const int jx = 32 * (wave >> 1), jy = 16 * wave;
+        auto gen = [&](int jc, int nb, int part) {
+            const int bx = __builtin_amdgcn_readfirstlane(jc + jx + 8 * part);
+            const int by = __builtin_amdgcn_readfirstlane(jc + jy + 4 * part);
+            V8 gxv;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float d = ka * xs[bx + i] - zxa;
+                const float e = fast_exp2(-(d * d));
+                gxv[i] = (T)(bx + i < n_in ? e : 0.f);
+            }
+            *(V8 *)&L.gx[nb][gcol][jx + 8 * part] = gxv;
+            V4 gyv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float d = ka * ys[by + i] - zya;
+                const float e = fast_exp2(-(d * d));
+                gyv[i] = (T)(by + i < n_in ? e : 0.f);
+            }
+            *(V4 *)&L.gy[nb][lane][jy + 4 * part] = gyv;
+            if (part == 0 && wave == 3) {
+                const int j = jc + lane;
+                float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+                if (j < n_in) {
+                    const float4 r0 = packed[2 * j], r1 = packed[2 * j + 1];
+                    const float4 qj = make_float4(1.f + r0.z, r0.w, r1.x, r1.y);
+                    const float4 qc = dq_mul(dq_mul(aq, qj), bq);
+                    v[0] = ch0m1 + ch0 * r0.z + sh0 * r0.w;   // q'_c - 1
+                    v[1] = qc.y;
+                    v[2] = qc.z;
+                    v[3] = qc.w;
+                    v[4] = r1.z - sm1;                          // s_j - s0
+                }
+#pragma unroll
+                for (int c = 0; c < 5; ++c) L.qd[nb][c][lane] = (typename HalfT<DT>::Q)v[c];
+            }
+        };
+        auto kstep = [&](int buf, int s) {
+            const int k8 = 16 * s + 8 * half;
+            const V8 a0 = *(const V8 *)&L.gy[buf][col][k8];
+            const V8 a1 = *(const V8 *)&L.gy[buf][32 + col][k8];
+            const V8 g = *(const V8 *)&L.gx[buf][32 * wave + col][k8];
+            V8 bop[6];
+            if constexpr (DT == kDtF16) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) bop[c] = g * *(const half8 *)&L.qd[buf][c][k8];
+            } else {
+                float gf[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) gf[i] = (float)g[i];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const float4 q0 = *(const float4 *)&L.qd[buf][c][k8];
+                    const float4 q1 = *(const float4 *)&L.qd[buf][c][k8 + 4];
+                    const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) bop[c][i] = (T)(gf[i] * qv[i]);
+                }
+            }
+            bop[5] = g;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                if constexpr (DT == kDtF16) {
+                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, bop[c], acc[0][c], 0, 0, 0);
+                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, bop[c], acc[1][c], 0, 0, 0);
+                } else {
+                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bop[c], acc[0][c], 0, 0, 0);
+                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bop[c], acc[1][c], 0, 0, 0);
+                }
+            }
+        };
+#pragma unroll
+        for (int part = 0; part < 4; ++part) gen(0, 0, part);
+        __syncthreads();
+        for (int c = 0; c < nchunks; ++c) {
+            const int buf = c & 1;
+            const bool more = c + 1 < nchunks;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                kstep(buf, s);
+                if (more) gen((c + 1) * kHK, buf ^ 1, s);
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- epilogue: undo the coding, DQ normalisation, Eq. (1)
+#pragma unroll
+    for (int bl = 0; bl < 2; ++bl)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int zx = px0 + 32 * wave + col;
+        const int zy = py0 + 32 * bl + 8 * (r >> 2) + 4 * half + (r & 3);
+        if (zx >= zx0 + w || zy >= zy0 + h) continue;
+        const float W = acc[bl][5][r];
+        const float C = acc[bl][0][r] + W, S = acc[bl][1][r];
+        const float X = acc[bl][2][r], Y = acc[bl][3][r];
+        const float in2 = 1.f / (C * C + S * S), in = sqrtf(in2);
+        const float ch = C * in, sh = S * in;
+        const float tx = 2.f * (C * X - S * Y) * in2, ty = 2.f * (S * X + C * Y) * in2;
+        const float chc = ch0 * ch - sh0 * sh, shc = sh0 * ch + ch0 * sh;   // R0 R'
+        const float ux = (float)zx - pcx, uy = (float)zy - pcy;
+        const float ex = -2.f * shc * shc * ux - 2.f * chc * shc * uy + cos0 * tx - sin0 * ty + d0x;
+        const float ey = 2.f * chc * shc * ux - 2.f * shc * shc * uy + sin0 * tx + cos0 * ty + d0y;
+        const float sg = sm1 + acc[bl][4][r] / W;
+        const float fzx = (float)zx, fzy = (float)zy;
+        const float2 d = make_float2(ex + sg * (fzx + ex), ey + sg * (fzy + ey));
+        if constexpr (MODE == kModeField) {
+            out[(size_t)(zy - zy0) * w + (zx - zx0)] =
+                bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
+                    : make_float2(fzx + d.x, fzy + d.y);
+        } else {
+            warp_merge(zx, zy, d, frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
+        }
+    }
+}
+
+// ---------------------------------------------- node tracking, uncertainty ----
+
+__device__ __forceinline__ float wave_min(float v) {
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// One tracking step of m deformation nodes against the model's inliers
+// (Sec. III-C and III-E), one wavefront per node, lanes over the inliers:
+//   (ds, dq) = blend at the node's position p (Eqs. (2)-(3)), normalised;
+//   dsig2 = exp(beta d_min^2), d_min the distance to the nearest inlier
+//           (Eq. (8): exp is increasing, so its minimum is at d_min);
+//   App. A: q1 = translation by (1 - s)/s times the translation of dq,
+//           q <- the motion "q, then dq, then q1", s <- ds s;
+//   Eq. (9): sig2 <- ds^2 sig2 + dsig2;   p <- ds dq(p)  (Eq. (1)).
+// A node with no weight (or a failed model) gets NaN everywhere.
+__global__ __launch_bounds__(kEmThreads) void k_track(
+    const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, float beta,
+    int m, float2 *__restrict__ pos, float *__restrict__ scale, float4 *__restrict__ q,
+    float *__restrict__ sig2) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int i = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
+    if (i >= m) return;
+    const int n_in = st->n_in;
+    const bool bad = st->status < 0 || n_in <= 0;
+    const float2 p = pos[i];
+    float W = 0.f, Gd = 0.f, Cd = 0.f, Sn = 0.f, X = 0.f, Y = 0.f;
+    float d2min = __builtin_huge_valf();
+    if (!bad)
+        for (int j = lane; j < n_in; j += kWave) {
+            const float4 r0 = packed[2 * j], r1 = packed[2 * j + 1];
+            const float dx = r0.x - p.x, dy = r0.y - p.y;
+            const float d2 = dx * dx + dy * dy;
+            const float w = fast_exp2(nal2 * d2);
+            W += w;
+            Cd += w * r0.z;
+            Sn += w * r0.w;
+            X += w * r1.x;
+            Y += w * r1.y;
+            Gd += w * r1.z;
+            d2min = fminf(d2min, d2);
+        }
+    W = wave_sum(W);
+    Gd = wave_sum(Gd);
+    Cd = wave_sum(Cd);
+    Sn = wave_sum(Sn);
+    X = wave_sum(X);
+    Y = wave_sum(Y);
+    d2min = wave_min(d2min);
+    if (lane != 0) return;
+    if (bad || !(W > 0.f)) {
+        const float nan = __builtin_nanf("");
+        pos[i] = make_float2(nan, nan);
+        scale[i] = nan;
+        q[i] = make_float4(nan, nan, nan, nan);
+        sig2[i] = nan;
+        return;
+    }
+    const float iW = 1.f / W;
+    const float c = 1.f + Cd * iW, sn = Sn * iW, bx = X * iW, by = Y * iW, ds = 1.f + Gd * iW;
+    const float in = 1.f / sqrtf(c * c + sn * sn);
+    const float4 dq = make_float4(c * in, sn * in, bx * in, by * in);
+    const float tx = 2.f * (dq.x * dq.z - dq.y * dq.w), ty = 2.f * (dq.y * dq.z + dq.x * dq.w);
+    const float2 d = blend_displacement(W, Cd, Sn, X, Y, Gd, p.x, p.y);
+    const float so = scale[i];
+    const float k = (1.f - so) / so;
+    const float4 q1 = make_float4(1.f, 0.f, 0.5f * k * tx, 0.5f * k * ty);
+    float4 qn = dq_mul(dq_mul(q1, dq), q[i]);
+    float nr = 1.f / sqrtf(qn.x * qn.x + qn.y * qn.y);
+    if (qn.x < 0.f) nr = -nr;   // canonical sign, q_c >= 0
+    q[i] = make_float4(qn.x * nr, qn.y * nr, qn.z * nr, qn.w * nr);
+    scale[i] = ds * so;
+    sig2[i] = ds * ds * sig2[i] + expf(beta * d2min);
+    pos[i] = make_float2(p.x + d.x, p.y + d.y);
+}
+
+// Eq. (8) at every grid point z = (zx0 + i, zy0 + k): exp(beta d_min(z)^2),
+// d_min the distance to the nearest inlier.  Workgroup tile 64 x 64 with
+// centre c and half-diagonal r.  If D is the distance from c to its nearest
+// inlier, every pixel of the tile has an inlier within D + r, and an inlier
+// farther than D + 2r from c is farther than D + r from every pixel: only
+// the inliers within D + 2r of c (plus 1 px against rounding) are scanned.
+// The minimum does not depend on the scan order, so the candidate list is
+// built with LDS atomics and the result is still deterministic.
+constexpr int kUTile = 64, kUChunk = 2048, kUThreads = 256;
+
+__global__ __launch_bounds__(kUThreads) void k_uncertainty(
+    const float4 *__restrict__ packed, const DevState *__restrict__ st, float beta, int zx0,
+    int zy0, int w, int h, int tiles_x, float *__restrict__ out) {
+    __shared__ float2 cand[kUChunk];
+    __shared__ float red[kUThreads / kWave];
+    __shared__ int ncand;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int n_in = st->n_in;
+    const bool bad = st->status < 0 || n_in <= 0;
+    const int px0 = zx0 + (int)(blockIdx.x % tiles_x) * kUTile;
+    const int py0 = zy0 + (int)(blockIdx.x / tiles_x) * kUTile;
+    const float cx = (float)px0 + 0.5f * (kUTile - 1), cy = (float)py0 + 0.5f * (kUTile - 1);
+    constexpr float kHalfDiag = 0.5f * (kUTile - 1) * 1.41421357f;
+    const int zx = px0 + lane;
+    float m2[kUTile / 4];
+#pragma unroll
+    for (int k = 0; k < kUTile / 4; ++k) m2[k] = __builtin_huge_valf();
+    if (!bad) {
+        float dmin = __builtin_huge_valf();
+        for (int j = tid; j < n_in; j += kUThreads) {
+            const float4 r0 = packed[2 * j];
+            const float dx = r0.x - cx, dy = r0.y - cy;
+            dmin = fminf(dmin, sqrtf(dx * dx + dy * dy));
+        }
+        dmin = wave_min(dmin);
+        if (lane == 0) red[wave] = dmin;
+        __syncthreads();
+        dmin = fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
+        const float lim = dmin + 2.f * kHalfDiag + 1.f;
+        for (int c0 = 0; c0 < n_in; c0 += kUChunk) {
+            if (tid == 0) ncand = 0;
+            __syncthreads();
+            const int c1 = min(c0 + kUChunk, n_in);
+            for (int j = c0 + tid; j < c1; j += kUThreads) {
+                const float4 r0 = packed[2 * j];
+                const float dx = r0.x - cx, dy = r0.y - cy;
+                if (sqrtf(dx * dx + dy * dy) <= lim) cand[atomicAdd(&ncand, 1)] = make_float2(r0.x, r0.y);
+            }
+            __syncthreads();
+            const int nc = ncand;
+            for (int t = 0; t < nc; ++t) {
+                const float2 v = cand[t];
+                const float ex = (float)zx - v.x, ax = ex * ex;
+#pragma unroll
+                for (int k = 0; k < kUTile / 4; ++k) {
+                    const float ey = (float)(py0 + wave + 4 * k) - v.y;
+                    m2[k] = fminf(m2[k], fmaf(ey, ey, ax));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (zx >= zx0 + w) return;
+#pragma unroll
+    for (int k = 0; k < kUTile / 4; ++k) {
+        const int zy = py0 + wave + 4 * k;
+        if (zy >= zy0 + h) break;
+        out[(size_t)(zy - zy0) * w + (zx - zx0)] = bad ? __builtin_nanf("") : expf(beta * m2[k]);
+    }
+}
+
+// ------------------------------------------------------ learned EM start ----
+//
+// A per-match inlier prior to start the EM from (not in the paper; the
+// start p = 1 stays the default).  Match i looks at its 16 nearest other
+// matches by source distance, ordered by (squared distance in FP64, index);
+// per neighbour j the features are g (x_j - x_i) and ss((d_j - d_i) / 8),
+// g = sqrt(alpha), d = dst - src, ss(t) = t / (1 + |t|); a 64 -> 128 -> 128
+// -> 1 network with GELU layers and a sigmoid output maps them to p.
+// Weights: W1[128][64], b1, W2[128][128], b2, w3[128], b3 (FP32, flat).
+constexpr int kKnn = 16, kNFeat = 4 * kKnn, kNHid = 128;
+constexpr int kStartWaves = 8, kStartThreads = kStartWaves * kWave;
+static_assert(kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid + kNHid + 1 == 24961,
+              "weight vector size stated in the header");
+
+struct alignas(16) StartLds {
+    float w1t[kNFeat][kNHid];   // transposed: lane o reads w1t[k][o]
+    float w2t[kNHid][kNHid];
+    float b1[kNHid], b2[kNHid], w3[kNHid];
+    float f[kStartWaves][kNFeat];
+    float h[kStartWaves][kNHid];
+};
+
+__device__ __forceinline__ float gelu(float t) {
+    return 0.5f * t * (1.f + erff(t * 0.70710678118654752f));
+}
+
+// (a, ia) < (b, ib) lexicographically
+__device__ __forceinline__ bool key_less(double a, int ia, double b, int ib) {
+    return a < b || (a == b && ia < ib);
+}
+
+__device__ __forceinline__ double dist2_f64(float2 a, float2 b) {
+#pragma clang fp contract(off)
+    const double dx = (double)b.x - (double)a.x, dy = (double)b.y - (double)a.y;
+    return dx * dx + dy * dy;   // rounded as written, no fused multiply-add
+}
+
+// LDS written by some lanes of a wavefront and read by others of the same
+// wavefront: keep the compiler from moving accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(kStartThreads) void k_start(
+    const float2 *__restrict__ src, const float2 *__restrict__ dst, int n, float g,
+    const float *__restrict__ wts, float *__restrict__ p_out) {
+    __shared__ StartLds L;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const float *W1 = wts, *B1 = W1 + kNHid * kNFeat, *W2 = B1 + kNHid;
+    const float *B2 = W2 + kNHid * kNHid, *W3 = B2 + kNHid, *B3 = W3 + kNHid;
+    for (int t = tid; t < kNHid * kNFeat; t += kStartThreads) L.w1t[t % kNFeat][t / kNFeat] = W1[t];
+    for (int t = tid; t < kNHid * kNHid; t += kStartThreads) L.w2t[t % kNHid][t / kNHid] = W2[t];
+    for (int t = tid; t < kNHid; t += kStartThreads) {
+        L.b1[t] = B1[t];
+        L.b2[t] = B2[t];
+        L.w3[t] = W3[t];
+    }
+    const float b3 = B3[0];
+    __syncthreads();
+
+    for (int i = blockIdx.x * kStartWaves + wave; i < n; i += gridDim.x * kStartWaves) {
+        const float2 xi = src[i];
+        // ---- per-lane sorted lists of the 16 nearest (lanes scan j in
+        // increasing order, so an equal distance never displaces an entry)
+        double bd[kKnn];
+        int bj[kKnn];
+#pragma unroll
+        for (int k = 0; k < kKnn; ++k) { bd[k] = __builtin_huge_val(); bj[k] = 0x7fffffff; }
+        for (int j = lane; j < n; j += kWave) {
+            if (j == i) continue;
+            const double d2 = dist2_f64(xi, src[j]);
+            if (!(d2 < bd[kKnn - 1])) continue;
+#pragma unroll
+            for (int k = kKnn - 1; k >= 1; --k) {
+                const bool shift = bd[k - 1] > d2;
+                const bool here = !shift && bd[k] > d2;
+                bd[k] = shift ? bd[k - 1] : (here ? d2 : bd[k]);
+                bj[k] = shift ? bj[k - 1] : (here ? j : bj[k]);
+            }
+            if (bd[0] > d2) { bd[0] = d2; bj[0] = j; }
+        }
+        // ---- merge: 16 rounds of a wavefront arg-min over the list heads
+        int my_nbr = -1;
+#pragma unroll 1
+        for (int r = 0; r < kKnn; ++r) {
+            double md = bd[0];
+            int mj = bj[0];
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double od = __shfl_xor(md, off, kWave);
+                const int oj = __shfl_xor(mj, off, kWave);
+                if (key_less(od, oj, md, mj)) { md = od; mj = oj; }
+            }
+            if (lane == r && mj != 0x7fffffff) my_nbr = mj;
+            if (bj[0] == mj && mj != 0x7fffffff) {   // the owner pops its head
+#pragma unroll
+                for (int k = 0; k < kKnn - 1; ++k) { bd[k] = bd[k + 1]; bj[k] = bj[k + 1]; }
+                bd[kKnn - 1] = __builtin_huge_val();
+                bj[kKnn - 1] = 0x7fffffff;
+            }
+        }
+        // ---- features (lane r < 16: neighbour r)
+        if (lane < kKnn) {
+            float4 fv = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (my_nbr >= 0) {
+                const float2 xj = src[my_nbr], yj = dst[my_nbr], yi = dst[i];
+                float ex = ((yj.x - xj.x) - (yi.x - xi.x)) * 0.125f;
+                float ey = ((yj.y - xj.y) - (yi.y - xi.y)) * 0.125f;
+                fv = make_float4(g * (xj.x - xi.x), g * (xj.y - xi.y), ex / (1.f + fabsf(ex)),
+                                 ey / (1.f + fabsf(ey)));
+            }
+            *(float4 *)&L.f[wave][4 * lane] = fv;
+        }
+        wave_sync();   // features are per wavefront: no workgroup barrier
+        // layer 1
+        float a0 = L.b1[lane], a1 = L.b1[lane + 64];
+#pragma unroll 8
+        for (int k = 0; k < kNFeat; ++k) {
+            const float fk = L.f[wave][k];
+            a0 = fmaf(L.w1t[k][lane], fk, a0);
+            a1 = fmaf(L.w1t[k][lane + 64], fk, a1);
+        }
+        L.h[wave][lane] = gelu(a0);
+        L.h[wave][lane + 64] = gelu(a1);
+        wave_sync();
+        // layer 2
+        float c0 = L.b2[lane], c1 = L.b2[lane + 64];
+#pragma unroll 8
+        for (int k = 0; k < kNHid; ++k) {
+            const float hk = L.h[wave][k];
+            c0 = fmaf(L.w2t[k][lane], hk, c0);
+            c1 = fmaf(L.w2t[k][lane + 64], hk, c1);
+        }
+        const float z = wave_sum(L.w3[lane] * gelu(c0) + L.w3[lane + 64] * gelu(c1)) + b3;
+        if (lane == 0) p_out[i] = 1.f / (1.f + expf(-z));
+        wave_sync();   // the next match overwrites this wavefront's rows
+    }
+}
+
+// EM start from given posteriors: xy as k_load, p = init_p, mask = p > thresh
+// (FP32); a non-finite start or coordinate sets ENONFINITE.
+__global__ void k_load_from(const float2 *__restrict__ src, const float2 *__restrict__ dst,
+                            const float *__restrict__ init_p, int n, float p_thresh,
+                            float4 *__restrict__ xy, float *__restrict__ p,
+                            uint8_t *__restrict__ mask, DevState *st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 a = src[i], b = dst[i];
+    const float pi = init_p[i];
+    xy[i] = make_float4(a.x, a.y, b.x, b.y);
+    p[i] = pi;
+    mask[i] = pi > p_thresh ? 1 : 0;
+    if (!finite2(a) || !finite2(b) || !__builtin_isfinite(pi)) {
+        atomicMin(&st->status, (int)EMDQ_ENONFINITE);
+        atomicExch(&st->done, 1);
+    }
+}
+
 constexpr int kSplitK = EMDQ_SPLITK;
+#ifndef EMDQ_ROWBLOCKS
+#define EMDQ_ROWBLOCKS 1
+#endif
+constexpr int kRowBlocks = EMDQ_ROWBLOCKS;
+
+// ---------------------------------------------------------------- batches ----
+//
+// Many independent pairs in one launch per phase.  Every pair keeps its own
+// model (buffers and DevState); a job table in device memory holds each
+// pair's pointers and sizes.  EM phases use a 2D grid (blockIdx.y = pair,
+// blockIdx.x = the pair's own workgroup, surplus workgroups of smaller pairs
+// return at once); the field launch is flat over the pairs' tiles, each
+// workgroup finding its pair by a binary search of the tile offsets.
+struct EmJob {
+    const float2 *src, *dst;
+    float4 *xy;
+    float *p;
+    uint8_t *mask;
+    float *e2;
+    float4 *q;
+    float *s;
+    float4 *packed;
+    float *xs, *ys;
+    DevState *st;
+    int n, blocks;       // matches; EM workgroups of this pair
+    float nal2;
+    double alpha, u;
+};
+
+struct FieldJob {
+    const float4 *packed;
+    const DevState *st;
+    float2 *out;
+    const uint8_t *frame;
+    float4 *canvas;
+    float nal2;
+    int zx0, zy0, w, h, tiles_x, n_tiles, block_base;
+    int fw, fh, fpitch, cpitch, ox, oy;
+};
+
+__global__ void k_reset_b(const EmJob *__restrict__ jobs) {
+    if (threadIdx.x == 0) reset_state(jobs[blockIdx.x].st);
+}
+
+__global__ void k_load_b(const EmJob *__restrict__ jobs) {
+    const EmJob &J = jobs[blockIdx.y];
+    if ((int)blockIdx.x * (int)blockDim.x >= J.n) return;
+    load_body(J.src, J.dst, J.n, J.xy, J.p, J.mask, J.st, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kEmThreads) void k_mstep_b(const EmJob *__restrict__ jobs,
+                                                        int final_pass) {
+    const EmJob &J = jobs[blockIdx.y];
+    if ((int)blockIdx.x >= J.blocks) return;
+    mstep_body(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.st, final_pass, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kEmThreads) void k_estep_b(const EmJob *__restrict__ jobs) {
+    const EmJob &J = jobs[blockIdx.y];
+    if ((int)blockIdx.x >= J.blocks) return;
+    estep_body(J.xy, J.p, J.q, J.s, J.n, J.nal2, J.e2, J.st, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kPostThreads) void k_posterior_b(
+    const EmJob *__restrict__ jobs, double sigma2_min, double gamma_min, double gamma_max,
+    float p_thresh, int max_iter) {
+    const EmJob &J = jobs[blockIdx.x];
+    posterior_body(J.p, J.e2, J.mask, J.n, J.u, sigma2_min, gamma_min, gamma_max, p_thresh,
+                   max_iter, J.st, 0);
+}
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact_b(const EmJob *__restrict__ jobs) {
+    const EmJob &J = jobs[blockIdx.x];
+    compact_body(J.xy, J.q, J.s, J.mask, J.n, J.packed, J.xs, J.ys, J.st, 0);
+}
+
+__global__ void k_gather_states(const EmJob *__restrict__ jobs, int n_pairs,
+                                DevState *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_pairs) out[i] = *jobs[i].st;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kFieldThreads) void k_field_b(const FieldJob *__restrict__ jobs,
+                                                           int n_jobs) {
+    int lo = 0, hi = n_jobs - 1;   // last job whose first workgroup is <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_base <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const FieldJob &J = jobs[lo];
+    field_body<MODE, kSplitK, kRowBlocks>(J.packed, J.st, J.nal2, J.zx0, J.zy0, J.w, J.h,
+                                          J.tiles_x, J.n_tiles, J.out, J.frame, J.fw, J.fh,
+                                          J.fpitch, J.canvas, J.cpitch, J.ox, J.oy,
+                                          (int)blockIdx.x - J.block_base);
+}
 
 }  // namespace
 
@@ -731,6 +1527,9 @@ struct emdq_model_s {
     float4 *q = nullptr;
     float *s = nullptr;
     float4 *packed = nullptr;
+    float *xs = nullptr;     // inlier coordinates, SoA, padded by one chunk
+    float *ys = nullptr;
+    int precision = EMDQ_PREC_F32;
     DevState *st = nullptr;
     DevState *host_st = nullptr;   // pinned
     hipStream_t last = nullptr;
@@ -759,21 +1558,45 @@ double alpha_d(const emdq_params &p, int w, int h) {
     return (double)p.alpha0 / (s * s);
 }
 
+emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int n,
+                     int frame_w, int frame_h, const emdq_params *params, const float *init_p,
+                     hipStream_t stream);
+
 emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h, float2 *out,
                          const uint8_t *frame, int fw, int fh, int fpitch, float4 *canvas,
                          int cpitch, int ox, int oy, hipStream_t stream) {
-    const int tiles_x = (w + kTile - 1) / kTile, tiles_y = (h + kTile - 1) / kTile;
+    const int tiles_x = (w + kTile - 1) / kTile;
+    const int tiles_y = (h + kTile * kRowBlocks - 1) / (kTile * kRowBlocks);
     const long long n_tiles = (long long)tiles_x * tiles_y;
     constexpr int tiles_per_wg = 4 / kSplitK;
     const long long blocks = (n_tiles + tiles_per_wg - 1) / tiles_per_wg;
     if (blocks > 0x7fffffffLL / kFieldThreads) return EMDQ_EINVAL;
+    if (m->precision != EMDQ_PREC_F32) {
+        const long long hx = (w + kHTx - 1) / kHTx, hy = (h + kHTy - 1) / kHTy;
+        if (hx * hy > 0x7fffffffLL) return EMDQ_EINVAL;
+        const unsigned nb = (unsigned)(hx * hy);
+        const float ka = sqrtf(m->alpha * kLog2e);
+        const bool f16 = m->precision == EMDQ_PREC_F16;
+        if (mode == kModeField) {
+            auto k = f16 ? k_field_half<kModeField, kDtF16> : k_field_half<kModeField, kDtBF16>;
+            hipLaunchKernelGGL(k, dim3(nb), dim3(kFieldThreads), 0, stream, m->packed, m->xs,
+                               m->ys, m->st, ka, zx0, zy0, w, h, (int)hx, out, nullptr, 0, 0,
+                               0, nullptr, 0, 0, 0);
+        } else {
+            auto k = f16 ? k_field_half<kModeWarp, kDtF16> : k_field_half<kModeWarp, kDtBF16>;
+            hipLaunchKernelGGL(k, dim3(nb), dim3(kFieldThreads), 0, stream, m->packed, m->xs,
+                               m->ys, m->st, ka, zx0, zy0, w, h, (int)hx, nullptr, frame, fw, fh,
+                               fpitch, canvas, cpitch, ox, oy);
+        }
+        return check_launch();
+    }
     const float nal2 = -m->alpha * kLog2e;
     if (mode == kModeField)
-        hipLaunchKernelGGL((k_field<kModeField, kSplitK>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((k_field<kModeField, kSplitK, kRowBlocks>), dim3((unsigned)blocks),
                            dim3(kFieldThreads), 0, stream, m->packed, m->st, nal2, zx0, zy0, w,
                            h, tiles_x, (int)n_tiles, out, nullptr, 0, 0, 0, nullptr, 0, 0, 0);
     else
-        hipLaunchKernelGGL((k_field<kModeWarp, kSplitK>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((k_field<kModeWarp, kSplitK, kRowBlocks>), dim3((unsigned)blocks),
                            dim3(kFieldThreads), 0, stream, m->packed, m->st, nal2, zx0, zy0, w,
                            h, tiles_x, (int)n_tiles, nullptr, frame, fw, fh, fpitch, canvas,
                            cpitch, ox, oy);
@@ -836,6 +1659,8 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     ok = ok && hipMalloc((void **)&m->q, n * sizeof(float4)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->s, n * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->packed, 2 * n * sizeof(float4)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&m->xs, (n + kHK) * sizeof(float)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&m->ys, (n + kHK) * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->st, sizeof(DevState)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&m->host_st, sizeof(DevState), hipHostMallocDefault) ==
                    hipSuccess;
@@ -863,6 +1688,8 @@ void emdq_model_free(emdq_model m) {
     (void)hipFree(m->q);
     (void)hipFree(m->s);
     (void)hipFree(m->packed);
+    (void)hipFree(m->xs);
+    (void)hipFree(m->ys);
     (void)hipFree(m->st);
     if (m->host_st) (void)hipHostFree(m->host_st);
     delete m;
@@ -870,6 +1697,16 @@ void emdq_model_free(emdq_model m) {
 
 emdq_status emdq_fit(emdq_model m, const float *src_xy, const float *dst_xy, int n,
                      int frame_w, int frame_h, const emdq_params *params,
+                     hipStream_t stream) {
+    return fit_impl(m, src_xy, dst_xy, n, frame_w, frame_h, params, nullptr, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int n,
+                     int frame_w, int frame_h, const emdq_params *params, const float *init_p,
                      hipStream_t stream) {
     if (!m || !src_xy || !dst_xy) return EMDQ_EINVAL;
     emdq_params prm;
@@ -886,9 +1723,14 @@ emdq_status emdq_fit(emdq_model m, const float *src_xy, const float *dst_xy, int
     const unsigned em_blocks = (unsigned)((n + kRowsPerBlock - 1) / kRowsPerBlock);
 
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, m->st);
-    hipLaunchKernelGGL(k_load, dim3((n + 255) / 256), dim3(256), 0, stream,
-                       (const float2 *)src_xy, (const float2 *)dst_xy, n, m->xy, m->p, m->mask,
-                       m->st);
+    if (init_p)
+        hipLaunchKernelGGL(k_load_from, dim3((n + 255) / 256), dim3(256), 0, stream,
+                           (const float2 *)src_xy, (const float2 *)dst_xy, init_p, n,
+                           prm.p_thresh, m->xy, m->p, m->mask, m->st);
+    else
+        hipLaunchKernelGGL(k_load, dim3((n + 255) / 256), dim3(256), 0, stream,
+                           (const float2 *)src_xy, (const float2 *)dst_xy, n, m->xy, m->p,
+                           m->mask, m->st);
     if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
     // EM: iterations are enqueued in chunks; every kernel returns at once
     // after the device-side stop flag is set, so a chunk may overshoot.
@@ -899,9 +1741,10 @@ emdq_status emdq_fit(emdq_model m, const float *src_xy, const float *dst_xy, int
             hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
                                m->p, n, nal2, alpha, m->q, m->s, m->st, 0);
             hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
-                               m->p, m->q, m->s, n, nal2, u, (double)prm.sigma2_min,
-                               (double)prm.gamma_min, (double)prm.gamma_max, prm.p_thresh,
-                               prm.max_iter, m->e2, m->mask, m->st);
+                               m->p, m->q, m->s, n, nal2, m->e2, m->st);
+            hipLaunchKernelGGL(k_posterior, dim3(1), dim3(kPostThreads), 0, stream, m->p, m->e2,
+                               m->mask, n, u, (double)prm.sigma2_min, (double)prm.gamma_min,
+                               (double)prm.gamma_max, prm.p_thresh, prm.max_iter, m->st);
         }
         if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
         EMDQ_HIP(hipMemcpyAsync(m->host_st, m->st, sizeof(DevState), hipMemcpyDeviceToHost,
@@ -913,9 +1756,13 @@ emdq_status emdq_fit(emdq_model m, const float *src_xy, const float *dst_xy, int
     hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy, m->p, n,
                        nal2, alpha, m->q, m->s, m->st, 1);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, stream, m->xy, m->q,
-                       m->s, m->mask, n, m->packed, m->st);
+                       m->s, m->mask, n, m->packed, m->xs, m->ys, m->st);
     return check_launch();
 }
+
+}  // namespace
+
+extern "C" {
 
 emdq_status emdq_model_set_nodes(emdq_model m, const float *x_xy, const float *scale,
                                  const float *q, const uint8_t *mask, int n, float alpha,
@@ -948,7 +1795,7 @@ emdq_status emdq_model_set_nodes(emdq_model m, const float *x_xy, const float *s
     if (rc == EMDQ_OK) {
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, m->st);
         hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, stream, m->xy, m->q,
-                           m->s, m->mask, n, m->packed, m->st);
+                           m->s, m->mask, n, m->packed, m->xs, m->ys, m->st);
         rc = check_launch();
     }
     // the staging buffers are released only after the copies completed
@@ -983,6 +1830,66 @@ emdq_status emdq_warp(emdq_model m, const uint8_t *frame_rgb, int fw, int fh,
                         frame_pitch_bytes, (float4 *)canvas, canvas_pitch_px, ox, oy, stream);
 }
 
+emdq_status emdq_track_nodes(emdq_model m, float beta, int n_nodes, float *pos_xy,
+                             float *scale, float *q, float *sigma2, hipStream_t stream) {
+    if (!m || n_nodes < 0 || !(beta > 0.f) || !__builtin_isfinite(beta)) return EMDQ_EINVAL;
+    if (n_nodes == 0) return EMDQ_OK;
+    if (!pos_xy || !scale || !q || !sigma2) return EMDQ_EINVAL;
+    if ((((uintptr_t)pos_xy) & 7u) || (((uintptr_t)q) & 15u)) return EMDQ_EINVAL;
+    m->last = stream;
+    const float nal2 = -m->alpha * kLog2e;
+    const unsigned blocks = (unsigned)((n_nodes + kRowsPerBlock - 1) / kRowsPerBlock);
+    hipLaunchKernelGGL(k_track, dim3(blocks), dim3(kEmThreads), 0, stream, m->packed, m->st,
+                       nal2, beta, n_nodes, (float2 *)pos_xy, scale, (float4 *)q, sigma2);
+    return check_launch();
+}
+
+emdq_status emdq_uncertainty(emdq_model m, float beta, int zx0, int zy0, int w, int h,
+                             float *out, hipStream_t stream) {
+    if (!m || !out || w < 0 || h < 0 || !(beta > 0.f) || !__builtin_isfinite(beta))
+        return EMDQ_EINVAL;
+    if (w == 0 || h == 0) return EMDQ_OK;
+    const long long tx = (w + kUTile - 1) / kUTile, ty = (h + kUTile - 1) / kUTile;
+    if (tx * ty > 0x7fffffffLL) return EMDQ_EINVAL;
+    m->last = stream;
+    hipLaunchKernelGGL(k_uncertainty, dim3((unsigned)(tx * ty)), dim3(kUThreads), 0, stream,
+                       m->packed, m->st, beta, zx0, zy0, w, h, (int)tx, out);
+    return check_launch();
+}
+
+emdq_status emdq_learned_start(const float *src_xy, const float *dst_xy, int n, int frame_w,
+                               int frame_h, const emdq_params *params, const float *weights,
+                               float *p_out, hipStream_t stream) {
+    if (!src_xy || !dst_xy || !weights || !p_out || frame_w <= 0 || frame_h <= 0)
+        return EMDQ_EINVAL;
+    if (n < 2) return EMDQ_ETOOFEW;
+    emdq_params prm;
+    if (params) prm = *params; else emdq_params_default(&prm);
+    if (!params_ok(prm)) return EMDQ_EINVAL;
+    const float g = (float)sqrt(alpha_d(prm, frame_w, frame_h));
+    int blocks = (n + kStartWaves - 1) / kStartWaves;
+    if (blocks > 1024) blocks = 1024;   // each workgroup stages the weights once
+    hipLaunchKernelGGL(k_start, dim3((unsigned)blocks), dim3(kStartThreads), 0, stream,
+                       (const float2 *)src_xy, (const float2 *)dst_xy, n, g, weights, p_out);
+    return check_launch();
+}
+
+emdq_status emdq_fit_from(emdq_model m, const float *src_xy, const float *dst_xy, int n,
+                          int frame_w, int frame_h, const emdq_params *params,
+                          const float *init_p, hipStream_t stream) {
+    if (!init_p) return EMDQ_EINVAL;
+    return fit_impl(m, src_xy, dst_xy, n, frame_w, frame_h, params, init_p, stream);
+}
+
+emdq_status emdq_model_set_precision(emdq_model m, emdq_precision precision) {
+    if (!m) return EMDQ_EINVAL;
+    if (precision != EMDQ_PREC_F32 && precision != EMDQ_PREC_F16 &&
+        precision != EMDQ_PREC_BF16)
+        return EMDQ_EINVAL;
+    m->precision = precision;
+    return EMDQ_OK;
+}
+
 emdq_status emdq_model_status(emdq_model m, hipStream_t stream) {
     if (!m) return EMDQ_EINVAL;
     EMDQ_HIP(hipMemcpyAsync(m->host_st, m->st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
@@ -1007,6 +1914,256 @@ emdq_status emdq_model_results(emdq_model m, float *scale, float *q, float *p, u
     if (sigma2) *sigma2 = s.sigma2;
     if (gamma) *gamma = s.gamma;
     return (emdq_status)s.status;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches ----
+
+struct emdq_batch_s {
+    int max_pairs = 0;
+    EmJob *em_jobs = nullptr;        // device
+    FieldJob *field_jobs = nullptr;  // device
+    DevState *states = nullptr;      // device, gathered per chunk
+    DevState *host_states = nullptr; // pinned
+    static constexpr int kSlots = 4; // pinned staging ring for the job tables
+    void *stage[kSlots] = {};
+    hipEvent_t stage_done[kSlots] = {};
+    int next_slot = 0;
+};
+
+namespace {
+
+size_t batch_stage_bytes(int max_pairs) {
+    const size_t a = sizeof(EmJob), b = sizeof(FieldJob);
+    return (a > b ? a : b) * (size_t)max_pairs;
+}
+
+// A staging slot whose previous upload has completed.
+void *batch_slot(emdq_batch b, int *slot) {
+    const int k = b->next_slot;
+    b->next_slot = (k + 1) % emdq_batch_s::kSlots;
+    if (hipEventSynchronize(b->stage_done[k]) != hipSuccess) return nullptr;
+    *slot = k;
+    return b->stage[k];
+}
+
+bool distinct_models(int n, const emdq_model *models) {
+    for (int i = 0; i < n; ++i) {
+        if (!models[i]) return false;
+        for (int j = 0; j < i; ++j)
+            if (models[i] == models[j]) return false;
+    }
+    return true;
+}
+
+emdq_status batch_region_ok(const emdq_region &r, int mode) {
+    if (r.w < 0 || r.h < 0) return EMDQ_EINVAL;
+    if (mode == kModeField) return (r.w && r.h && !r.out_xy) ? EMDQ_EINVAL : EMDQ_OK;
+    if (!r.frame_rgb || !r.canvas) return EMDQ_EINVAL;
+    if (r.fw <= 0 || r.fh <= 0 || r.cw <= 0 || r.ch <= 0) return EMDQ_EINVAL;
+    if ((long long)r.frame_pitch_bytes < 3LL * r.fw || r.canvas_pitch_px < r.cw)
+        return EMDQ_EINVAL;
+    if (((uintptr_t)r.canvas & 15u) != 0) return EMDQ_EINVAL;
+    const long long cx0 = (long long)r.zx0 + r.ox, cy0 = (long long)r.zy0 + r.oy;
+    if (r.w && r.h && (cx0 < 0 || cy0 < 0 || cx0 + r.w > r.cw || cy0 + r.h > r.ch))
+        return EMDQ_EINVAL;
+    return EMDQ_OK;
+}
+
+emdq_status batch_field_launch(emdq_batch b, int n_pairs, const emdq_model *models,
+                               const emdq_region *regions, int mode, hipStream_t stream) {
+    if (!b || !models || !regions || n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (!models[i]) return EMDQ_EINVAL;
+        const emdq_status rc = batch_region_ok(regions[i], mode);
+        if (rc != EMDQ_OK) return rc;
+    }
+    int slot = 0;
+    FieldJob *jobs = (FieldJob *)batch_slot(b, &slot);
+    if (!jobs) return EMDQ_EHIP;
+    constexpr int tiles_per_wg = 4 / kSplitK;
+    long long base = 0;
+    for (int i = 0; i < n_pairs; ++i) {
+        const emdq_region &r = regions[i];
+        emdq_model m = models[i];
+        FieldJob &J = jobs[i];
+        const int tiles_x = (r.w + kTile - 1) / kTile;
+        const int tiles_y = (r.h + kTile * kRowBlocks - 1) / (kTile * kRowBlocks);
+        const long long n_tiles = (r.w && r.h) ? (long long)tiles_x * tiles_y : 0;
+        J.packed = m->packed;
+        J.st = m->st;
+        J.nal2 = -m->alpha * kLog2e;
+        J.zx0 = r.zx0;
+        J.zy0 = r.zy0;
+        J.w = r.w;
+        J.h = r.h;
+        J.tiles_x = tiles_x;
+        J.n_tiles = (int)n_tiles;
+        J.block_base = (int)base;
+        J.out = (float2 *)r.out_xy;
+        J.frame = r.frame_rgb;
+        J.fw = r.fw;
+        J.fh = r.fh;
+        J.fpitch = r.frame_pitch_bytes;
+        J.canvas = (float4 *)r.canvas;
+        J.cpitch = r.canvas_pitch_px;
+        J.ox = r.ox;
+        J.oy = r.oy;
+        base += (n_tiles + tiles_per_wg - 1) / tiles_per_wg;
+        if (base > 0x7fffffffLL / kFieldThreads) return EMDQ_EINVAL;
+        m->last = stream;
+    }
+    if (base == 0) return EMDQ_OK;
+    EMDQ_HIP(hipMemcpyAsync(b->field_jobs, jobs, sizeof(FieldJob) * n_pairs,
+                            hipMemcpyHostToDevice, stream));
+    EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
+    if (mode == kModeField)
+        hipLaunchKernelGGL(k_field_b<kModeField>, dim3((unsigned)base), dim3(kFieldThreads), 0,
+                           stream, b->field_jobs, n_pairs);
+    else
+        hipLaunchKernelGGL(k_field_b<kModeWarp>, dim3((unsigned)base), dim3(kFieldThreads), 0,
+                           stream, b->field_jobs, n_pairs);
+    return check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+emdq_status emdq_batch_create(int max_pairs, emdq_batch *out) {
+    if (!out || max_pairs < 1 || max_pairs > 65535) return EMDQ_EINVAL;
+    *out = nullptr;
+    emdq_batch b = new (std::nothrow) emdq_batch_s;
+    if (!b) return EMDQ_ENOMEM;
+    b->max_pairs = max_pairs;
+    const size_t n = (size_t)max_pairs;
+    bool ok = hipMalloc((void **)&b->em_jobs, n * sizeof(EmJob)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->field_jobs, n * sizeof(FieldJob)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->states, n * sizeof(DevState)) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->host_states, n * sizeof(DevState),
+                             hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; ok && k < emdq_batch_s::kSlots; ++k) {
+        ok = hipHostMalloc(&b->stage[k], batch_stage_bytes(max_pairs), hipHostMallocDefault) ==
+             hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&b->stage_done[k], hipEventDisableTiming) ==
+                       hipSuccess;
+    }
+    if (!ok) {
+        emdq_batch_free(b);
+        return EMDQ_ENOMEM;
+    }
+    *out = b;
+    return EMDQ_OK;
+}
+
+void emdq_batch_free(emdq_batch b) {
+    if (!b) return;
+    for (int k = 0; k < emdq_batch_s::kSlots; ++k) {
+        if (b->stage_done[k]) {
+            (void)hipEventSynchronize(b->stage_done[k]);
+            (void)hipEventDestroy(b->stage_done[k]);
+        }
+        if (b->stage[k]) (void)hipHostFree(b->stage[k]);
+    }
+    (void)hipFree(b->em_jobs);
+    (void)hipFree(b->field_jobs);
+    (void)hipFree(b->states);
+    if (b->host_states) (void)hipHostFree(b->host_states);
+    delete b;
+}
+
+emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
+                           const float *const *src_xy, const float *const *dst_xy,
+                           const int *n, const int *frame_w, const int *frame_h,
+                           const emdq_params *params, hipStream_t stream) {
+    if (!b || !models || !src_xy || !dst_xy || !n || !frame_w || !frame_h) return EMDQ_EINVAL;
+    if (n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
+    if (!distinct_models(n_pairs, models)) return EMDQ_EINVAL;
+    emdq_params prm;
+    if (params) prm = *params; else emdq_params_default(&prm);
+    if (!params_ok(prm)) return EMDQ_EINVAL;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (!src_xy[i] || !dst_xy[i] || frame_w[i] <= 0 || frame_h[i] <= 0) return EMDQ_EINVAL;
+        if (n[i] < 2) return EMDQ_ETOOFEW;
+        if (n[i] > models[i]->n_max) return EMDQ_EINVAL;
+    }
+    int slot = 0;
+    EmJob *jobs = (EmJob *)batch_slot(b, &slot);
+    if (!jobs) return EMDQ_EHIP;
+    int max_blocks = 1, max_n = 2;
+    for (int i = 0; i < n_pairs; ++i) {
+        emdq_model m = models[i];
+        const double alpha = alpha_d(prm, frame_w[i], frame_h[i]);
+        m->n = n[i];
+        m->alpha = (float)alpha;
+        m->last = stream;
+        EmJob &J = jobs[i];
+        J.src = (const float2 *)src_xy[i];
+        J.dst = (const float2 *)dst_xy[i];
+        J.xy = m->xy;
+        J.p = m->p;
+        J.mask = m->mask;
+        J.e2 = m->e2;
+        J.q = m->q;
+        J.s = m->s;
+        J.packed = m->packed;
+        J.xs = m->xs;
+        J.ys = m->ys;
+        J.st = m->st;
+        J.n = n[i];
+        J.blocks = (n[i] + kRowsPerBlock - 1) / kRowsPerBlock;
+        J.nal2 = -(float)alpha * kLog2e;
+        J.alpha = alpha;
+        J.u = 1.0 / ((double)frame_w[i] * (double)frame_h[i]);
+        if (J.blocks > max_blocks) max_blocks = J.blocks;
+        if (n[i] > max_n) max_n = n[i];
+    }
+    EMDQ_HIP(hipMemcpyAsync(b->em_jobs, jobs, sizeof(EmJob) * n_pairs, hipMemcpyHostToDevice,
+                            stream));
+    EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
+    const unsigned P = (unsigned)n_pairs;
+    hipLaunchKernelGGL(k_reset_b, dim3(P), dim3(64), 0, stream, b->em_jobs);
+    hipLaunchKernelGGL(k_load_b, dim3((unsigned)((max_n + 255) / 256), P), dim3(256), 0, stream,
+                       b->em_jobs);
+    if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
+    int enqueued = 0;
+    const int chunk = 4;
+    while (true) {
+        for (int c = 0; c < chunk && enqueued < prm.max_iter; ++c, ++enqueued) {
+            hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0,
+                               stream, b->em_jobs, 0);
+            hipLaunchKernelGGL(k_estep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0,
+                               stream, b->em_jobs);
+            hipLaunchKernelGGL(k_posterior_b, dim3(P), dim3(kPostThreads), 0, stream,
+                               b->em_jobs, (double)prm.sigma2_min, (double)prm.gamma_min,
+                               (double)prm.gamma_max, prm.p_thresh, prm.max_iter);
+        }
+        hipLaunchKernelGGL(k_gather_states, dim3((P + 63) / 64), dim3(64), 0, stream,
+                           b->em_jobs, n_pairs, b->states);
+        if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
+        EMDQ_HIP(hipMemcpyAsync(b->host_states, b->states, sizeof(DevState) * n_pairs,
+                                hipMemcpyDeviceToHost, stream));
+        EMDQ_HIP(hipStreamSynchronize(stream));
+        bool all = true;
+        for (int i = 0; i < n_pairs; ++i)
+            all = all && (b->host_states[i].done || b->host_states[i].status < 0);
+        if (all || enqueued >= prm.max_iter) break;
+    }
+    hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0, stream,
+                       b->em_jobs, 1);
+    hipLaunchKernelGGL(k_compact_b, dim3(P), dim3(kCompactThreads), 0, stream, b->em_jobs);
+    return check_launch();
+}
+
+emdq_status emdq_batch_field(emdq_batch b, int n_pairs, const emdq_model *models,
+                             const emdq_region *regions, hipStream_t stream) {
+    return batch_field_launch(b, n_pairs, models, regions, kModeField, stream);
+}
+
+emdq_status emdq_batch_warp(emdq_batch b, int n_pairs, const emdq_model *models,
+                            const emdq_region *regions, hipStream_t stream) {
+    return batch_field_launch(b, n_pairs, models, regions, kModeWarp, stream);
 }
 
 }  // extern "C"

@@ -19,7 +19,16 @@ OK, WARN_NOT_CONVERGED, EINVAL, ETOOFEW, ENOINLIERS, ENONFINITE, EHIP, ENOMEM = 
 # every function declared in include/emdq.h
 EXPORTS = ("emdq_params_default", "emdq_alpha", "emdq_model_create", "emdq_model_free",
            "emdq_fit", "emdq_model_set_nodes", "emdq_field", "emdq_warp",
-           "emdq_model_status", "emdq_model_results", "emdq_status_string")
+           "emdq_uncertainty", "emdq_track_nodes", "emdq_model_set_precision",
+           "emdq_model_status", "emdq_model_results", "emdq_status_string",
+           "emdq_batch_create", "emdq_batch_free", "emdq_batch_fit", "emdq_batch_field",
+           "emdq_batch_warp", "emdq_fit_from", "emdq_learned_start")
+
+START_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "start_mlp.npy")
+N_START_WEIGHTS = 24961
+
+PREC_F32, PREC_F16, PREC_BF16 = 0, 1, 2
+PRECISIONS = {"f32": PREC_F32, "f16": PREC_F16, "bf16": PREC_BF16}
 
 
 class Params(C.Structure):
@@ -27,6 +36,15 @@ class Params(C.Structure):
     _fields_ = [("alpha0", C.c_float), ("ref_w", C.c_int), ("ref_h", C.c_int),
                 ("max_iter", C.c_int), ("p_thresh", C.c_float), ("gamma_min", C.c_float),
                 ("gamma_max", C.c_float), ("sigma2_min", C.c_float), ("flags", C.c_uint)]
+
+
+class Region(C.Structure):
+    """emdq_region."""
+    _fields_ = [("zx0", C.c_int), ("zy0", C.c_int), ("w", C.c_int), ("h", C.c_int),
+                ("out_xy", C.c_void_p), ("frame_rgb", C.c_void_p), ("fw", C.c_int),
+                ("fh", C.c_int), ("frame_pitch_bytes", C.c_int), ("canvas", C.c_void_p),
+                ("cw", C.c_int), ("ch", C.c_int), ("canvas_pitch_px", C.c_int),
+                ("ox", C.c_int), ("oy", C.c_int)]
 
 
 class EmdqError(RuntimeError):
@@ -57,17 +75,39 @@ def lib():
         L.emdq_model_free.restype = None
         L.emdq_fit.argtypes = [P, P, P, I, I, I, C.POINTER(Params), P]
         L.emdq_fit.restype = I
+        L.emdq_fit_from.argtypes = [P, P, P, I, I, I, C.POINTER(Params), P, P]
+        L.emdq_fit_from.restype = I
+        L.emdq_learned_start.argtypes = [P, P, I, I, I, C.POINTER(Params), P, P, P]
+        L.emdq_learned_start.restype = I
         L.emdq_model_set_nodes.argtypes = [P, P, P, P, P, I, F, P]
         L.emdq_model_set_nodes.restype = I
         L.emdq_field.argtypes = [P, I, I, I, I, P, P]
         L.emdq_field.restype = I
         L.emdq_warp.argtypes = [P, U8P, I, I, I, P, I, I, I, I, I, I, I, I, I, P]
         L.emdq_warp.restype = I
+        L.emdq_uncertainty.argtypes = [P, F, I, I, I, I, P, P]
+        L.emdq_uncertainty.restype = I
+        L.emdq_track_nodes.argtypes = [P, F, I, P, P, P, P, P]
+        L.emdq_track_nodes.restype = I
+        L.emdq_model_set_precision.argtypes = [P, I]
+        L.emdq_model_set_precision.restype = I
         L.emdq_model_status.argtypes = [P, P]
         L.emdq_model_status.restype = I
         L.emdq_model_results.argtypes = [P, P, P, P, P, C.POINTER(I), C.POINTER(I),
                                          C.POINTER(F), C.POINTER(F), P]
         L.emdq_model_results.restype = I
+        L.emdq_batch_create.argtypes = [I, C.POINTER(P)]
+        L.emdq_batch_create.restype = I
+        L.emdq_batch_free.argtypes = [P]
+        L.emdq_batch_free.restype = None
+        PP = C.POINTER(C.c_void_p)
+        IP = C.POINTER(C.c_int)
+        L.emdq_batch_fit.argtypes = [P, I, PP, PP, PP, IP, IP, IP, C.POINTER(Params), P]
+        L.emdq_batch_fit.restype = I
+        L.emdq_batch_field.argtypes = [P, I, PP, C.POINTER(Region), P]
+        L.emdq_batch_field.restype = I
+        L.emdq_batch_warp.argtypes = [P, I, PP, C.POINTER(Region), P]
+        L.emdq_batch_warp.restype = I
         L.emdq_status_string.argtypes = [I]
         L.emdq_status_string.restype = C.c_char_p
         _lib = L
@@ -137,6 +177,48 @@ def emdq_fit(model: int, src, dst, frame_w: int, frame_h: int, params: Params | 
                                  _stream(stream)), "emdq_fit")
 
 
+def emdq_fit_from(model: int, src, dst, frame_w: int, frame_h: int, init_p,
+                  params: Params | None = None, stream=None) -> int:
+    """As emdq_fit, starting from init_p (CUDA float32 [N])."""
+    import torch
+    if src.shape != dst.shape or src.dim() != 2 or src.shape[1] != 2:
+        raise ValueError("src and dst must both be [N, 2]")
+    if tuple(init_p.shape) != (src.shape[0],):
+        raise ValueError("init_p must be [N]")
+    ps = _dev(src, torch.float32, "src")
+    pd = _dev(dst, torch.float32, "dst")
+    pp = _dev(init_p, torch.float32, "init_p")
+    return _check(lib().emdq_fit_from(model, ps, pd, int(src.shape[0]), int(frame_w),
+                                      int(frame_h), C.byref(params) if params is not None
+                                      else None, pp, _stream(stream)), "emdq_fit_from")
+
+
+def load_start_weights(device="cuda", path=None):
+    """The trained weights of the learned EM start as a CUDA float32 tensor."""
+    import numpy as np
+    import torch
+    w = np.load(path or START_WEIGHTS, allow_pickle=False).astype(np.float32)
+    if w.shape != (N_START_WEIGHTS,):
+        raise ValueError(f"expected {N_START_WEIGHTS} weights, got {w.shape}")
+    return torch.from_numpy(w).to(device)
+
+
+def emdq_learned_start(src, dst, frame_w: int, frame_h: int, weights, out,
+                       params: Params | None = None, stream=None) -> int:
+    """Learned starting posteriors: src, dst CUDA float32 [N, 2]; weights
+    CUDA float32 [24961]; out CUDA float32 [N]."""
+    import torch
+    if src.shape != dst.shape or src.dim() != 2 or src.shape[1] != 2:
+        raise ValueError("src and dst must both be [N, 2]")
+    if tuple(out.shape) != (src.shape[0],) or tuple(weights.shape) != (N_START_WEIGHTS,):
+        raise ValueError("out must be [N] and weights [24961]")
+    return _check(lib().emdq_learned_start(
+        _dev(src, torch.float32, "src"), _dev(dst, torch.float32, "dst"), int(src.shape[0]),
+        int(frame_w), int(frame_h), C.byref(params) if params is not None else None,
+        _dev(weights, torch.float32, "weights"), _dev(out, torch.float32, "out"),
+        _stream(stream)), "emdq_learned_start")
+
+
 def emdq_model_set_nodes(model: int, x_xy, scale, q, mask, alpha: float, stream=None) -> int:
     """Host (numpy) arrays: x_xy [N, 2], scale [N], q [N, 4] float32, mask [N] uint8."""
     import numpy as np
@@ -180,6 +262,41 @@ def emdq_warp(model: int, frame, canvas, ox: int, oy: int, zx0: int, zy0: int, w
                                   w, h, _stream(stream)), "emdq_warp")
 
 
+def emdq_uncertainty(model: int, beta: float, zx0: int, zy0: int, w: int, h: int, out,
+                     stream=None) -> int:
+    """out: CUDA float32 [h, w]."""
+    import torch
+    if tuple(out.shape) != (h, w):
+        raise ValueError("out must be [h, w]")
+    po = _dev(out, torch.float32, "out")
+    return _check(lib().emdq_uncertainty(model, float(beta), zx0, zy0, w, h, po,
+                                         _stream(stream)), "emdq_uncertainty")
+
+
+def emdq_track_nodes(model: int, beta: float, pos, scale, q, sigma2, stream=None) -> int:
+    """CUDA float32 tensors, updated in place: pos [n, 2], scale [n], q [n, 4],
+    sigma2 [n]."""
+    import torch
+    n = int(scale.shape[0]) if scale.dim() == 1 else -1
+    if n < 0 or tuple(pos.shape) != (n, 2) or tuple(q.shape) != (n, 4) or \
+            tuple(sigma2.shape) != (n,):
+        raise ValueError("shapes must be pos [n,2], scale [n], q [n,4], sigma2 [n]")
+    args = [_dev(t, torch.float32, name) for t, name in
+            ((pos, "pos"), (scale, "scale"), (q, "q"), (sigma2, "sigma2"))]
+    return _check(lib().emdq_track_nodes(model, float(beta), n, *args, _stream(stream)),
+                  "emdq_track_nodes")
+
+
+def emdq_model_set_precision(model: int, precision) -> int:
+    """precision: PREC_F32 / PREC_F16 / PREC_BF16 or "f32" / "f16" / "bf16"."""
+    if isinstance(precision, str):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        precision = PRECISIONS[precision]
+    return _check(lib().emdq_model_set_precision(model, int(precision)),
+                  "emdq_model_set_precision")
+
+
 def emdq_model_status(model: int, stream=None) -> int:
     return lib().emdq_model_status(model, _stream(stream))
 
@@ -211,6 +328,10 @@ class Model:
         self.n = int(src.shape[0])
         return emdq_fit(self.handle, src, dst, frame_w, frame_h, params, stream)
 
+    def fit_from(self, src, dst, frame_w, frame_h, init_p, params=None, stream=None):
+        self.n = int(src.shape[0])
+        return emdq_fit_from(self.handle, src, dst, frame_w, frame_h, init_p, params, stream)
+
     def set_nodes(self, x_xy, scale, q, mask, alpha, stream=None):
         self.n = int(len(scale))
         return emdq_model_set_nodes(self.handle, x_xy, scale, q, mask, alpha, stream)
@@ -221,6 +342,15 @@ class Model:
     def warp(self, frame, canvas, ox, oy, zx0, zy0, w, h, stream=None):
         return emdq_warp(self.handle, frame, canvas, ox, oy, zx0, zy0, w, h, stream)
 
+    def uncertainty(self, beta, zx0, zy0, w, h, out, stream=None):
+        return emdq_uncertainty(self.handle, beta, zx0, zy0, w, h, out, stream)
+
+    def track_nodes(self, beta, pos, scale, q, sigma2, stream=None):
+        return emdq_track_nodes(self.handle, beta, pos, scale, q, sigma2, stream)
+
+    def set_precision(self, precision):
+        return emdq_model_set_precision(self.handle, precision)
+
     def status(self, stream=None):
         return emdq_model_status(self.handle, stream)
 
@@ -230,6 +360,85 @@ class Model:
     def close(self):
         if self.handle:
             emdq_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns an emdq_batch handle: many pairs, one launch per phase."""
+
+    def __init__(self, max_pairs: int):
+        h = C.c_void_p()
+        _check(lib().emdq_batch_create(int(max_pairs), C.byref(h)), "emdq_batch_create")
+        self.handle = h.value
+        self.max_pairs = int(max_pairs)
+
+    @staticmethod
+    def _handles(models):
+        return (C.c_void_p * len(models))(*[m.handle for m in models])
+
+    def fit(self, models, srcs, dsts, sizes, params=None, stream=None):
+        """models: list of Model; srcs, dsts: CUDA float32 [N_i, 2];
+        sizes: list of (frame_w, frame_h)."""
+        import torch
+        k = len(models)
+        if not (len(srcs) == len(dsts) == len(sizes) == k):
+            raise ValueError("models, srcs, dsts and sizes must have the same length")
+        ps, pd, ns = [], [], []
+        for m, a, b in zip(models, srcs, dsts):
+            if a.shape != b.shape or a.dim() != 2 or a.shape[1] != 2:
+                raise ValueError("src and dst must both be [N, 2]")
+            ps.append(_dev(a, torch.float32, "src"))
+            pd.append(_dev(b, torch.float32, "dst"))
+            ns.append(int(a.shape[0]))
+            m.n = int(a.shape[0])
+        arr = lambda v, t: (t * k)(*v)
+        return _check(lib().emdq_batch_fit(
+            self.handle, k, self._handles(models), arr(ps, C.c_void_p), arr(pd, C.c_void_p),
+            arr(ns, C.c_int), arr([w for w, _ in sizes], C.c_int),
+            arr([h for _, h in sizes], C.c_int),
+            C.byref(params) if params is not None else None, _stream(stream)),
+            "emdq_batch_fit")
+
+    def field(self, models, rects, outs, stream=None):
+        """rects: list of (zx0, zy0, w, h); outs: CUDA float32 [h, w, 2]."""
+        import torch
+        regs = (Region * len(models))()
+        for r, (zx0, zy0, w, h), o in zip(regs, rects, outs):
+            if tuple(o.shape) != (h, w, 2):
+                raise ValueError("out must be [h, w, 2]")
+            r.zx0, r.zy0, r.w, r.h = zx0, zy0, w, h
+            r.out_xy = _dev(o, torch.float32, "out")
+        return _check(lib().emdq_batch_field(self.handle, len(models), self._handles(models),
+                                             regs, _stream(stream)), "emdq_batch_field")
+
+    def warp(self, models, frames, canvases, offsets, rects, stream=None):
+        """frames: CUDA uint8 [fh, fw, 3]; canvases: CUDA float32 [ch, cw, 4];
+        offsets: (ox, oy); rects: (zx0, zy0, w, h)."""
+        import torch
+        regs = (Region * len(models))()
+        for r, f, c, (ox, oy), (zx0, zy0, w, h) in zip(regs, frames, canvases, offsets, rects):
+            if f.dim() != 3 or f.shape[2] != 3 or c.dim() != 3 or c.shape[2] != 4:
+                raise ValueError("frame must be [fh, fw, 3] and canvas [ch, cw, 4]")
+            r.zx0, r.zy0, r.w, r.h = zx0, zy0, w, h
+            r.frame_rgb = _dev(f, torch.uint8, "frame")
+            r.fh, r.fw = int(f.shape[0]), int(f.shape[1])
+            r.frame_pitch_bytes = 3 * r.fw
+            r.canvas = _dev(c, torch.float32, "canvas")
+            r.ch, r.cw = int(c.shape[0]), int(c.shape[1])
+            r.canvas_pitch_px = r.cw
+            r.ox, r.oy = ox, oy
+        return _check(lib().emdq_batch_warp(self.handle, len(models), self._handles(models),
+                                            regs, _stream(stream)), "emdq_batch_warp")
+
+    def close(self):
+        if self.handle:
+            lib().emdq_batch_free(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["PairConfig", "CONFIGS", "gen_pair", "gen_config", "gen_texture",
-           "config_seed", "canvas_layout"]
+           "config_seed", "canvas_layout", "gen_batch", "BATCH_FRAMES"]
 
 
 @dataclass(frozen=True)
@@ -174,3 +174,23 @@ def similarity_matches(n: int, width: int, height: int, theta: float, scale: flo
     dst = c + scale * np.stack([ct * d[:, 0] - st * d[:, 1], st * d[:, 0] + ct * d[:, 1]], 1)
     dst = dst + np.asarray(shift, dtype=np.float64)
     return src, dst.astype(np.float32)
+
+
+# Mixed batch of independent pairs: frame size drawn from these, N ~ U[300, 3000],
+# outlier rate ~ U(0.10, 0.40), 8 bumps of 15 px and sigma 80 px.
+BATCH_FRAMES = ((640, 480), (1280, 1024), (1920, 1080))
+
+
+def gen_batch(n_pairs: int = 64, seed: int = 3000, with_frame: bool = True):
+    """A batch of `n_pairs` pairs of uneven size.  The shapes are drawn first
+    from `seed` (frame index, N, outlier rate per pair, in that order); pair i
+    is then drawn by gen_pair with seed 1000 * seed + i."""
+    rng = np.random.default_rng(seed)
+    pairs = []
+    for i in range(n_pairs):
+        w, h = BATCH_FRAMES[int(rng.integers(0, len(BATCH_FRAMES)))]
+        n = int(rng.integers(300, 3001))
+        rate = float(rng.uniform(0.10, 0.40))
+        cfg = PairConfig(w, h, n, rate, 8, 15.0, 80.0, w, h)
+        pairs.append(gen_pair(cfg, 1000 * seed + i, with_frame))
+    return pairs

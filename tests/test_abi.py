@@ -22,7 +22,7 @@ def test_library_exports_every_declared_function():
     from paper_2103_07414_amd import emdq as E
     L = E.lib()
     names = header_functions()
-    assert len(names) == 11
+    assert len(names) == 21
     assert sorted(E.EXPORTS) == names
     for name in names:
         assert hasattr(L, name), name
@@ -45,7 +45,18 @@ def test_host_only_calls():
     assert L.emdq_fit(None, None, None, 4, 10, 10, None, None) == E.EINVAL
     assert L.emdq_field(None, 0, 0, 1, 1, None, None) == E.EINVAL
     assert L.emdq_model_status(None, None) == E.EINVAL
+    assert L.emdq_model_set_precision(None, E.PREC_F16) == E.EINVAL
+    assert L.emdq_uncertainty(None, 1e-3, 0, 0, 4, 4, None, None) == E.EINVAL
+    assert L.emdq_track_nodes(None, 1e-3, 4, None, None, None, None, None) == E.EINVAL
+    assert L.emdq_batch_create(0, C.byref(h)) == E.EINVAL
+    assert L.emdq_batch_fit(None, 1, None, None, None, None, None, None, None, None) == E.EINVAL
+    assert L.emdq_batch_warp(None, 1, None, None, None) == E.EINVAL
+    L.emdq_batch_free(None)
+    assert L.emdq_fit_from(None, None, None, 4, 10, 10, None, None, None) == E.EINVAL
+    assert L.emdq_learned_start(None, None, 4, 10, 10, None, None, None, None) == E.EINVAL
     L.emdq_model_free(None)
+    with pytest.raises(ValueError):
+        E.emdq_model_set_precision(None, "f8")
 
 
 def test_binding_has_no_cpu_path():
@@ -53,3 +64,12 @@ def test_binding_has_no_cpu_path():
     from paper_2103_07414_amd import emdq as E
     src = open(E.__file__).read()
     assert "oracle" not in src.replace("there is no CPU fallback", "")
+
+
+def test_start_weights_file():
+    """The trained learned-start weights ship in-tree, load without pickle
+    and have the size the header states."""
+    from paper_2103_07414_amd import emdq as E
+    w = np.load(E.START_WEIGHTS, allow_pickle=False)
+    assert w.dtype == np.float32 and w.shape == (E.N_START_WEIGHTS,) == (O.N_WEIGHTS,)
+    assert np.isfinite(w).all()

@@ -1,0 +1,111 @@
+"""Batched pairs: one launch per EM phase for all pairs, one flat launch for
+all fields / warps.  The batch must give exactly the bits of the single-pair
+calls (same kernels, same per-pair arithmetic), and through them the
+oracle's masks, iteration counts and field tolerance."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2103_07414_amd import synth
+
+from gpu_util import FIELD_TOL_PX, emdq, to_dev, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch_and_singles(torch, pairs):
+    E = emdq()
+    k = len(pairs)
+    srcs = [to_dev(p.src, torch) for p in pairs]
+    dsts = [to_dev(p.dst, torch) for p in pairs]
+    sizes = [(p.cfg.width, p.cfg.height) for p in pairs]
+    mb = [E.Model(p.cfg.n_matches) for p in pairs]
+    ms = [E.Model(p.cfg.n_matches) for p in pairs]
+    b = E.Batch(k)
+    b.fit(mb, srcs, dsts, sizes)
+    for m, s, d, (w, h) in zip(ms, srcs, dsts, sizes):
+        m.fit(s, d, w, h)
+    return E, b, mb, ms
+
+
+def test_batch_fit_and_field_bit_identical_to_single_calls():
+    torch = torch_or_skip()
+    pairs = synth.gen_batch(6, seed=3007, with_frame=False)
+    E, b, mb, ms = _batch_and_singles(torch, pairs)
+    rects, outs_b, outs_s = [], [], []
+    for p, m in zip(pairs, ms):
+        W, H = p.cfg.width, p.cfg.height
+        rects.append((0, 0, W, H))
+        outs_b.append(torch.empty((H, W, 2), dtype=torch.float32, device="cuda"))
+        o = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+        m.field(0, 0, W, H, o)
+        outs_s.append(o)
+    b.field(mb, rects, outs_b)
+    for i, (x, y) in enumerate(zip(mb, ms)):
+        rx, ry = x.results(), y.results()
+        assert rx["status"] == ry["status"] and rx["iters"] == ry["iters"], i
+        for key in ("p", "q", "scale", "mask"):
+            assert np.array_equal(rx[key], ry[key]), (i, key)
+        assert torch.equal(outs_b[i], outs_s[i]), i
+
+
+def test_batch_against_oracle():
+    """Masks, iterations and the sampled field of every pair of a mixed
+    batch against the oracle."""
+    torch = torch_or_skip()
+    pairs = synth.gen_batch(5, seed=3011, with_frame=False)
+    E, b, mb, _ = _batch_and_singles(torch, pairs)
+    rects, outs = [], []
+    for p in pairs:
+        rects.append((0, 0, p.cfg.width, p.cfg.height))
+        outs.append(torch.empty((p.cfg.height, p.cfg.width, 2), dtype=torch.float32,
+                                device="cuda"))
+    b.field(mb, rects, outs)
+    for i, (p, m, o) in enumerate(zip(pairs, mb, outs)):
+        ref = O.fit(p.src, p.dst, p.cfg.width, p.cfg.height)
+        r = m.results()
+        assert np.array_equal(r["mask"], ref.mask) and r["iters"] == ref.iters, i
+        rng = np.random.default_rng(i)
+        pts = rng.integers(0, [p.cfg.width, p.cfg.height], (1500, 2)).astype(np.float64)
+        _, want = O.field_points(p.src, ref.scale, ref.q, ref.mask, ref.alpha, pts)
+        g = o.cpu().numpy()[pts[:, 1].astype(int), pts[:, 0].astype(int)]
+        err = np.abs(g - want).max()
+        print(f"pair {i} {p.cfg.width}x{p.cfg.height} N={p.cfg.n_matches}: iters {r['iters']} "
+              f"n_in {r['n_in']} field err {err:.2e} px", flush=True)
+        assert err <= FIELD_TOL_PX
+
+
+def test_batch_warp_bit_identical_to_single_warps():
+    torch = torch_or_skip()
+    pairs = synth.gen_batch(4, seed=3013)
+    E, b, mb, ms = _batch_and_singles(torch, pairs)
+    cb, cs, offs, rects, frames = [], [], [], [], []
+    for p in pairs:
+        W, H = p.cfg.width, p.cfg.height
+        init = torch.full((H + 8, W + 8, 4), 3.0, dtype=torch.float32, device="cuda")
+        cb.append(init.clone())
+        cs.append(init.clone())
+        offs.append((4, 4))
+        rects.append((0, 0, W, H))
+        frames.append(to_dev(p.frame, torch))
+    b.warp(mb, frames, cb, offs, rects)
+    for m, f, c, (W, H) in zip(ms, frames, cs, [(p.cfg.width, p.cfg.height) for p in pairs]):
+        m.warp(f, c, 4, 4, 0, 0, W, H)
+    for i in range(len(pairs)):
+        assert torch.equal(cb[i], cs[i]), i
+
+
+def test_batch_argument_errors():
+    torch = torch_or_skip()
+    E = emdq()
+    pairs = synth.gen_batch(2, seed=3017, with_frame=False)
+    m = E.Model(3000)
+    b = E.Batch(2)
+    src = [to_dev(p.src, torch) for p in pairs]
+    dst = [to_dev(p.dst, torch) for p in pairs]
+    sizes = [(p.cfg.width, p.cfg.height) for p in pairs]
+    with pytest.raises(E.EmdqError):          # the same model twice
+        b.fit([m, m], src, dst, sizes)
+    b3 = E.Batch(1)
+    with pytest.raises(E.EmdqError):          # more pairs than the batch holds
+        b3.fit([m, E.Model(3000)], src, dst, sizes)

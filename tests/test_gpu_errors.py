@@ -40,13 +40,17 @@ def test_nonfinite_coordinates_reported():
     m = E.Model(P.cfg.n_matches)
     m.fit(to_dev(P.src, torch), to_dev(dst, torch), 320, 240)
     assert m.status() == E.ENONFINITE
-    # after the error the field is NaN and the canvas is left as is
-    out = torch.zeros((8, 8, 2), dtype=torch.float32, device="cuda")
-    m.field(0, 0, 8, 8, out)
-    assert torch.isnan(out).all()
-    cv = torch.full((16, 16, 4), 7.0, dtype=torch.float32, device="cuda")
-    m.warp(to_dev(P.frame, torch), cv, 0, 0, 0, 0, 16, 16)
-    assert (cv == 7.0).all()
+    # after the error the field is NaN and the canvas is left as is, in
+    # every precision
+    for prec in ("f32", "f16", "bf16"):
+        m.set_precision(prec)
+        out = torch.zeros((8, 8, 2), dtype=torch.float32, device="cuda")
+        m.field(0, 0, 8, 8, out)
+        assert torch.isnan(out).all(), prec
+        cv = torch.full((16, 16, 4), 7.0, dtype=torch.float32, device="cuda")
+        m.warp(to_dev(P.frame, torch), cv, 0, 0, 0, 0, 16, 16)
+        assert (cv == 7.0).all(), prec
+    m.set_precision("f32")
     # the model recovers with the next good fit
     m.fit(to_dev(P.src, torch), to_dev(P.dst, torch), 320, 240)
     assert m.status() == E.OK
