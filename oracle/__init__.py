@@ -65,6 +65,8 @@ def lib():
                                       _D, _U8, C.POINTER(I), C.POINTER(Dd), C.POINTER(Dd)]
         L.oracle_init_features.argtypes = [I, _D, _D, Dd, _D]
         L.oracle_init_mlp.argtypes = [I, _D, _D, _D]
+        L.oracle_start_grad.restype = Dd
+        L.oracle_start_grad.argtypes = [I, _D, _D, _D, _D]
         L.oracle_field.restype = I
         L.oracle_field.argtypes = [I, _D, _D, _D, _U8, Dd, I, I, I, I, _D]
         L.oracle_field_points.restype = I
@@ -316,3 +318,12 @@ def init_mlp(feat, weights):
     out = np.zeros(feat.shape[0])
     lib().oracle_init_mlp(feat.shape[0], feat, w, out)
     return out
+
+
+def start_grad(feat, label, weights):
+    """Mean BCE of the learned start and its gradient -> (loss, grad [24961])."""
+    feat, label = _d(feat), _d(label)
+    w = _d(weights, (N_WEIGHTS,))
+    g = np.zeros(N_WEIGHTS)
+    loss = lib().oracle_start_grad(feat.shape[0], feat, label, w, g)
+    return loss, g

@@ -691,3 +691,65 @@ void oracle_init_mlp(int n, const double *feat, const double *w, double *p_out)
         p_out[i] = 1.0 / (1.0 + exp(-z));
     }
 }
+
+/* Mean binary cross-entropy of the learned start over n labelled samples
+ * (label 1 = inlier) and its gradient with respect to the flat weight vector
+ * (same layout as oracle_init_mlp), by the chain rule written out layer by
+ * layer; gelu'(t) = Phi(t) + t phi(t).  grad: [N_WEIGHTS], overwritten. */
+double oracle_start_grad(int n, const double *feat, const double *label, const double *w,
+                         double *grad)
+{
+    const double *W1 = w, *b1 = W1 + OR_NH * OR_NF, *W2 = b1 + OR_NH;
+    const double *b2 = W2 + OR_NH * OR_NH, *w3 = b2 + OR_NH, *b3 = w3 + OR_NH;
+    double *gW1 = grad, *gb1 = gW1 + OR_NH * OR_NF, *gW2 = gb1 + OR_NH;
+    double *gb2 = gW2 + OR_NH * OR_NH, *gw3 = gb2 + OR_NH, *gb3 = gw3 + OR_NH;
+    const int nw = OR_NH * OR_NF + OR_NH + OR_NH * OR_NH + OR_NH + OR_NH + 1;
+    for (int k = 0; k < nw; ++k) grad[k] = 0.0;
+    double loss = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double *f = feat + (size_t)i * OR_NF;
+        double a1[OR_NH], h1[OR_NH], a2[OR_NH], h2[OR_NH], d2[OR_NH], d1[OR_NH];
+        for (int o = 0; o < OR_NH; ++o) {
+            double a = b1[o];
+            for (int k = 0; k < OR_NF; ++k) a += W1[o * OR_NF + k] * f[k];
+            a1[o] = a;
+            h1[o] = gelu(a);
+        }
+        for (int o = 0; o < OR_NH; ++o) {
+            double a = b2[o];
+            for (int k = 0; k < OR_NH; ++k) a += W2[o * OR_NH + k] * h1[k];
+            a2[o] = a;
+            h2[o] = gelu(a);
+        }
+        double z = b3[0];
+        for (int k = 0; k < OR_NH; ++k) z += w3[k] * h2[k];
+        double y = label[i];
+        /* loss = softplus(z) - y z, stable form */
+        loss += (z > 0 ? z + log1p(exp(-z)) : log1p(exp(z))) - y * z;
+        double dz = 1.0 / (1.0 + exp(-z)) - y;
+        gb3[0] += dz;
+        for (int o = 0; o < OR_NH; ++o) {
+            gw3[o] += dz * h2[o];
+            double t = a2[o];
+            double dg = 0.5 * (1.0 + erf(t / sqrt(2.0))) + t * exp(-0.5 * t * t) / sqrt(2.0 * M_PI);
+            d2[o] = dz * w3[o] * dg;
+        }
+        for (int o = 0; o < OR_NH; ++o) {
+            gb2[o] += d2[o];
+            for (int k = 0; k < OR_NH; ++k) gW2[o * OR_NH + k] += d2[o] * h1[k];
+        }
+        for (int k = 0; k < OR_NH; ++k) {
+            double s = 0.0;
+            for (int o = 0; o < OR_NH; ++o) s += W2[o * OR_NH + k] * d2[o];
+            double t = a1[k];
+            double dg = 0.5 * (1.0 + erf(t / sqrt(2.0))) + t * exp(-0.5 * t * t) / sqrt(2.0 * M_PI);
+            d1[k] = s * dg;
+        }
+        for (int o = 0; o < OR_NH; ++o) {
+            gb1[o] += d1[o];
+            for (int k = 0; k < OR_NF; ++k) gW1[o * OR_NF + k] += d1[o] * f[k];
+        }
+    }
+    for (int k = 0; k < nw; ++k) grad[k] /= n;
+    return loss / n;
+}

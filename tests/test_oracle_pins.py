@@ -678,3 +678,36 @@ def test_fit_from_start_points():
     assert np.array_equal(lab.mask, plain.mask) and lab.iters <= plain.iters
     bad = O.fit(P.src, P.dst, 320, 240, init_p=np.full(200, np.nan))
     assert bad.status == O.ENONFINITE
+
+
+def test_start_grad_matches_torch_autograd_and_finite_differences():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(9)
+    w = rng.normal(0, 0.2, O.N_WEIGHTS)
+    f = rng.normal(0, 1, (40, 64))
+    y = (rng.uniform(size=40) > 0.3).astype(np.float64)
+    loss, g = O.start_grad(f, y, w)
+    wt = torch.from_numpy(w.copy()).requires_grad_(True)
+    nh, nf = O.N_HIDDEN, O.N_FEAT
+    o = [0]
+    def take(m):
+        t = wt[o[0]:o[0] + m]
+        o[0] += m
+        return t
+    W1 = take(nh * nf).reshape(nh, nf); b1 = take(nh)
+    W2 = take(nh * nh).reshape(nh, nh); b2 = take(nh)
+    w3 = take(nh); b3 = take(1)
+    h = torch.nn.functional.gelu(torch.from_numpy(f) @ W1.T + b1)
+    h = torch.nn.functional.gelu(h @ W2.T + b2)
+    z = h @ w3 + b3
+    lt = torch.nn.functional.binary_cross_entropy_with_logits(z, torch.from_numpy(y))
+    lt.backward()
+    assert loss == pytest.approx(lt.item(), rel=1e-12)
+    assert np.allclose(g, wt.grad.numpy(), rtol=1e-9, atol=1e-13)
+    # central differences on a few weights of every block
+    for k in [0, 8191, 8192 + 5, 8320 + 77, 24704 + 3, 24832 + 100, 24960]:
+        e = np.zeros_like(w)
+        e[k] = 1e-6
+        lp, _ = O.start_grad(f, y, w + e)
+        lm, _ = O.start_grad(f, y, w - e)
+        assert (lp - lm) / 2e-6 == pytest.approx(g[k], rel=1e-5, abs=1e-9)
