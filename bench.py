@@ -15,6 +15,10 @@ Workloads (--workload):
   batch64     64 independent pairs of mixed size (640x480 / 1280x1024 /
               1920x1080, N in [300, 3000], 10-40 % outliers), one canvas each,
               fitted and warped with the batched entry points
+  batch64-learned
+              the same, with the EM of every pair started from the learned
+              prior (batched learned start + batched fit from it); both batch
+              workloads also report plain single-pair calls on the same pairs
 
 Prints one JSON line.  value = frame pixels x steps / wall time of the timed
 steps (Mpix/s).  The roofline object covers the field + warp kernel, timed
@@ -36,9 +40,10 @@ METRIC = "Mpix/s dense EMDQ field+warp (N=2000); EM iters & px error learned vs 
 PEAK_TFLOPS = {"f32": 157.3, "f16": 2500.0, "bf16": 2500.0}
 # HBM traffic of the production field + warp kernel per launch, from rocprofv3
 # FETCH_SIZE + WRITE_SIZE (KiB per dispatch) scaled by the copy-kernel
-# calibration; None until measured for the current kernel.
-TRAFFIC_BYTES = None
-WORKLOADS = ("production", "fhd-f32", "fhd-f16", "fhd-bf16", "batch64")
+# calibration (factors 2.0 and 1.0): 14445.9 KiB x 2.0 + 18814.1 KiB x 1.0.
+# Set to None whenever the kernel changes, until the counters are taken again.
+TRAFFIC_BYTES = round((14445.9 * 2.0 + 18814.1 * 1.0) * 1024)
+WORKLOADS = ("production", "fhd-f32", "fhd-f16", "fhd-bf16", "batch64", "batch64-learned")
 
 
 def parse():
@@ -143,6 +148,44 @@ def learned_vs_plain(E, torch, P, model, src, dst, stream, reps=5):
     return res
 
 
+def truth_error(torch, pairs, models):
+    """Mean over pairs of the rms field error against the generator's truth
+    at 2000 sampled pixels per pair."""
+    errs = []
+    for P, m in zip(pairs, models):
+        W, H = P.cfg.width, P.cfg.height
+        rng = np.random.default_rng(P.seed)
+        ix, iy = rng.integers(0, W, 2000), rng.integers(0, H, 2000)
+        fld = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+        m.field(0, 0, W, H, fld)
+        f = fld.cpu().numpy()[iy, ix].astype(np.float64)
+        t = P.truth_map(np.stack([ix, iy], 1).astype(np.float64))
+        errs.append(np.sqrt(np.mean(np.sum((f - t) ** 2, 1))))
+    return round(float(np.mean(errs)), 4)
+
+
+def plain_sequential(E, torch, pairs, srcs, dsts, frames, canvases, layouts, sizes, stream,
+                     reps=3):
+    """The same pairs through plain single-pair calls (emdq_fit with p = 1,
+    then emdq_warp), one pair after the other: frames/s and field error."""
+    models = [E.Model(P.cfg.n_matches) for P in pairs]
+
+    def run():
+        for m, s_, d_, f_, c_, (cw, ch, ox, oy), (w, h) in zip(models, srcs, dsts, frames,
+                                                                canvases, layouts, sizes):
+            m.fit(s_, d_, w, h, stream=stream)
+            m.warp(f_, c_, ox, oy, 0, 0, w, h, stream=stream)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(frames_per_s=round(len(pairs) * reps / wall, 2),
+                px_err_vs_truth_rms_mean=truth_error(torch, pairs, models))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -162,7 +205,9 @@ def main():
     stream = torch.cuda.current_stream()
     wl = args.workload
     prec = {"fhd-f16": "f16", "fhd-bf16": "bf16"}.get(wl, "f32")
-    if wl == "batch64":
+    batched = wl.startswith("batch64")
+    learned = wl == "batch64-learned"
+    if batched:
         pairs = synth.gen_batch(64)
     else:
         pairs = [synth.gen_config(2 if wl == "production" else 4, args.pair)]
@@ -176,10 +221,16 @@ def main():
     canvases = [torch.zeros((ch, cw, 4), dtype=torch.float32, device=dev)
                 for cw, ch, _, _ in layouts]
     sizes = [(P.cfg.width, P.cfg.height) for P in pairs]
-    batch = E.Batch(len(pairs)) if wl == "batch64" else None
+    batch = E.Batch(len(pairs)) if batched else None
+    if learned:
+        start_w = E.load_start_weights()
+        starts = [torch.empty(P.cfg.n_matches, dtype=torch.float32, device=dev) for P in pairs]
 
     def step(ev=None):
-        if batch is not None:
+        if learned:
+            batch.learned_start(srcs, dsts, sizes, start_w, starts, stream=stream)
+            batch.fit(models, srcs, dsts, sizes, stream=stream, init_ps=starts)
+        elif batch is not None:
             batch.fit(models, srcs, dsts, sizes, stream=stream)
         else:
             models[0].fit(srcs[0], dsts[0], *sizes[0], stream=stream)
@@ -229,9 +280,10 @@ def main():
         workload = ("single frame pair, plain EMDQ at production size: 1280x1024 RGB uint8 "
                     "frame, N=2000 matches (30% outliers, 8 bumps amp 15 px sigma 80 px), "
                     "field + bilinear warp + merge into a 4096x4096 RGBA FP32 canvas")
-    elif wl == "batch64":
+    elif batched:
         workload = ("64 independent pairs of mixed size (640x480 / 1280x1024 / 1920x1080, "
-                    "N 300-3000, 10-40% outliers), batched fit + batched warp, one canvas each")
+                    "N 300-3000, 10-40% outliers), batched fit + batched warp, one canvas each"
+                    + (", EM started from the learned prior" if learned else ""))
     else:
         workload = (f"single 1920x1080 pair, N=4000 (30% outliers), field + warp into a "
                     f"1920x1080 RGBA FP32 canvas, blend operands {prec}")
@@ -251,6 +303,11 @@ def main():
     if wl == "production":
         out["learned_init"] = learned_vs_plain(E, torch, pairs[0], models[0], srcs[0], dsts[0],
                                                stream)
+    if batched:
+        out["this_form"] = dict(frames_per_s=round(len(pairs) * args.steps / wall, 2),
+                                px_err_vs_truth_rms_mean=truth_error(torch, pairs, models))
+        out["plain_single_pair_calls"] = plain_sequential(E, torch, pairs, srcs, dsts, frames,
+                                                          canvases, layouts, sizes, stream)
     if not args.no_cpu_baseline:
         sample = pairs[:1] if len(pairs) == 1 else pairs[:4]
         fits, cpu = cpu_baseline(sample, args.cpu_seconds)

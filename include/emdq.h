@@ -33,8 +33,9 @@
  * Memory and streams
  *   Every buffer argument is a device pointer unless marked "host".  The
  *   caller owns all buffers; the library owns the model, whose device memory
- *   is allocated once by emdq_model_create and freed by emdq_model_free.  No
- *   other call allocates.  All work is enqueued on the caller's stream in
+ *   is allocated once by emdq_model_create and freed by emdq_model_free
+ *   (plus the half-precision tables, allocated by emdq_model_set_precision).
+ *   No compute call allocates.  All work is enqueued on the caller's stream in
  *   order; a model must not be used from two streams at once.  Calls are
  *   deterministic: the same inputs give bit-identical outputs.
  *
@@ -142,6 +143,36 @@ emdq_status emdq_learned_start(const float *src_xy, const float *dst_xy, int n, 
                                int frame_h, const emdq_params *params, const float *weights,
                                float *p_out, hipStream_t stream);
 
+/* The learned start's 64 features of every match (definition as for
+ * emdq_learned_start), for training: feat_out device float[n][64]. */
+emdq_status emdq_start_features(const float *src_xy, const float *dst_xy, int n, int frame_w,
+                                int frame_h, const emdq_params *params, float *feat_out,
+                                hipStream_t stream);
+
+/* Floats of workspace emdq_start_train_step needs for `groups` workgroups:
+ * (groups + 1) * 24962.  0 for groups < 1.  Host function. */
+size_t emdq_start_train_work_floats(int groups);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * learned start's weights for the mean binary cross-entropy of a minibatch:
+ *   weights, adam_m, adam_v  device float[24961], updated in place (the
+ *            moments start at zero; step counts from 1 for the bias
+ *            correction);
+ *   feat     device float[m_samples][64], label device float[m_samples]
+ *            (1 = inlier),
+ *   idx      device int[batch], the minibatch's sample indices into them
+ *            (an index outside [0, m_samples) is skipped, but still counts
+ *            in the batch mean);
+ *   groups   workgroups sharing the minibatch (<= 4096, capped at batch);
+ *   work     device float workspace of emdq_start_train_work_floats(groups)
+ *            floats; after the step, work[groups * 24962 + k] holds the
+ *            minibatch gradient (k < 24961) and the mean loss (k = 24961).
+ * Deterministic for fixed groups.  EINVAL on null pointers or bad sizes. */
+emdq_status emdq_start_train_step(float *weights, float *adam_m, float *adam_v, int step,
+                                  const float *feat, const float *label, int m_samples,
+                                  const int *idx, int batch, float lr, int groups, float *work,
+                                  hipStream_t stream);
+
 /* Loads per-node warp functions directly (Eq. (1) per node, as the SLAM
  * nodes of Sec. III carry them) instead of fitting: host arrays
  *   x_xy float[n][2] node positions at time 0, scale float[n],
@@ -226,8 +257,11 @@ typedef enum {
 } emdq_precision;
 
 /* Selects the arithmetic of later emdq_field / emdq_warp calls on this
- * model (host-side setting, nothing is enqueued).  EINVAL on a null model
- * or an unknown value. */
+ * model (host-side setting, nothing is enqueued).  The first switch to F16
+ * or BF16 allocates the model's factor tables, 2 x 4096 rows of n_max
+ * (rounded up to 64) 16-bit values (about 16 KB per unit of n_max), kept
+ * until emdq_model_free; regions larger than 4096 in either direction are
+ * processed in slabs.  EINVAL on a null model or an unknown value; ENOMEM. */
 emdq_status emdq_model_set_precision(emdq_model m, emdq_precision precision);
 
 /* ------------------------------------------------------------ batches ---
@@ -235,7 +269,8 @@ emdq_status emdq_model_set_precision(emdq_model m, emdq_precision precision);
  * launch per phase instead of one per pair and phase: the EM phases of all
  * pairs run side by side, and the field / warp of all pairs is one flat
  * launch over their tiles.  Results are read per model (emdq_model_status,
- * emdq_model_results) and are bit-identical to the single-pair calls.  A
+ * emdq_model_results) and, with the default field-kernel shape, are
+ * bit-identical to the single-pair calls.  A
  * batch object holds only the job tables (device) and a few pinned staging
  * buffers; like a model, it is used from one stream at a time. */
 typedef struct emdq_batch_s *emdq_batch;
@@ -262,14 +297,26 @@ void emdq_batch_free(emdq_batch b);
 /* emdq_fit of n_pairs pairs at once (host arrays of n_pairs entries):
  * pair i fits n[i] matches src_xy[i] -> dst_xy[i] (device float[n[i]][2])
  * of a frame_w[i] x frame_h[i] frame into models[i], with one params for
- * all (null: defaults).  The models must be distinct.  Synchronises the
- * stream a few times to read the EM stop flags of all pairs.  EINVAL /
- * ETOOFEW as for emdq_fit (any pair), EHIP; per-pair outcomes are read with
+ * all (null: defaults).  init_p: null for the plain start of every pair,
+ * or n_pairs device pointers to starting posteriors (float[n[i]], as
+ * emdq_fit_from).  The models must be distinct.  Synchronises the stream a
+ * few times to read the EM stop flags of all pairs.  EINVAL / ETOOFEW as for
+ * emdq_fit (any pair), EHIP; per-pair outcomes are read with
  * emdq_model_status. */
 emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
                            const float *const *src_xy, const float *const *dst_xy,
                            const int *n, const int *frame_w, const int *frame_h,
-                           const emdq_params *params, hipStream_t stream);
+                           const float *const *init_p, const emdq_params *params,
+                           hipStream_t stream);
+
+/* emdq_learned_start of n_pairs pairs in one launch (host arrays of n_pairs
+ * entries; p_out[i] device float[n[i]]).  EINVAL / ETOOFEW as for
+ * emdq_learned_start on any pair. */
+emdq_status emdq_batch_learned_start(emdq_batch b, int n_pairs, const float *const *src_xy,
+                                     const float *const *dst_xy, const int *n,
+                                     const int *frame_w, const int *frame_h,
+                                     const emdq_params *params, const float *weights,
+                                     float *const *p_out, hipStream_t stream);
 
 /* emdq_field of every pair (FP32 blend) in one launch: models[i] over
  * regions[i] (host array).  EINVAL as for emdq_field on any region. */
@@ -281,6 +328,36 @@ emdq_status emdq_batch_field(emdq_batch b, int n_pairs, const emdq_model *models
  * concurrently.  EINVAL as for emdq_warp on any region. */
 emdq_status emdq_batch_warp(emdq_batch b, int n_pairs, const emdq_model *models,
                             const emdq_region *regions, hipStream_t stream);
+
+/* Autotuner of the batched field / warp launch: the field kernel comes in
+ * three shapes (split-K 4, 2, 1: four wavefronts on one 32 x 32 tile, two
+ * tiles, or four tiles per workgroup).  Times each shape on emdq_batch_field
+ * of these pairs and regions (which it therefore writes), keeps the fastest
+ * for later batched calls and stores it in *variant_out (nullable).  With a
+ * cache_path (nullable, host file), the choice is first looked up there by
+ * (rounded log2 of the total tile count, rounded log2 of the mean match
+ * count) and, when timed, appended as a text line.  Synchronises the
+ * stream.  EINVAL as for emdq_batch_field; EHIP. */
+emdq_status emdq_batch_autotune(emdq_batch b, int n_pairs, const emdq_model *models,
+                                const emdq_region *regions, const char *cache_path,
+                                int *variant_out, hipStream_t stream);
+
+/* Selects the field-kernel shape of later batched calls (0, 1, 2 as above). */
+emdq_status emdq_batch_set_variant(emdq_batch b, int variant);
+
+/* Builds the job table of a batched field (warp = 0) or warp (warp = 1)
+ * launch in the batch's device memory, synchronously (host-blocking, on the
+ * null stream), for emdq_batch_launch.  The models' current fits are read at
+ * launch time, so the same prepared launch serves later fits of the same
+ * models into the same buffers.  EINVAL as for emdq_batch_field /
+ * emdq_batch_warp. */
+emdq_status emdq_batch_prepare(emdq_batch b, int warp, int n_pairs, const emdq_model *models,
+                               const emdq_region *regions);
+
+/* Enqueues the prepared launch: one kernel, no copy and no allocation, so it
+ * can be captured in a hipGraph and replayed.  EINVAL if nothing is
+ * prepared. */
+emdq_status emdq_batch_launch(emdq_batch b, hipStream_t stream);
 
 /* Waits for `stream` and returns the outcome of the last fit or
  * set_nodes: OK, WARN_NOT_CONVERGED, ENONFINITE, ENOINLIERS. */

@@ -24,7 +24,9 @@
 // Every reduction has a fixed order, and there are no floating-point atomics,
 // so results are bit-reproducible.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -53,6 +55,13 @@ constexpr int kBufferFlags = 0x00020000;   // raw buffer resource word 3 (gfx9 f
 #endif
 
 constexpr int kRing = EMDQ_RING;       // field kernel: record ring depth (K steps)
+#ifndef EMDQ_HALF_TABLES
+#define EMDQ_HALF_TABLES 1  // half-precision blend: factor tables instead of in-loop exps
+#endif
+#ifndef EMDQ_EM_CHUNK
+#define EMDQ_EM_CHUNK 2
+#endif
+constexpr int kEmChunk = EMDQ_EM_CHUNK; // EM iterations enqueued between stop-flag reads
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -82,6 +91,13 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// LDS written by some lanes of a wavefront and read by others of the same
+// wavefront: keep the compiler from moving accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 __device__ __forceinline__ bool finite2(float2 v) {
     return __builtin_isfinite(v.x) && __builtin_isfinite(v.y);
@@ -703,15 +719,6 @@ __device__ __forceinline__ void field_body(
         const int kb = __builtin_amdgcn_readfirstlane(ks * kper);
         const int kend = kb + kper;
         const int voff = half * 32;        // lanes 32..63 take the odd inlier
-        auto load = [&](int j0, float4 &r0, float4 &r1) {
-            const int jj = __builtin_amdgcn_readfirstlane(min(j0, n_in));
-            const int bytes = __builtin_amdgcn_readfirstlane((n_in - jj) * 32);
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(packed + 2 * jj), (short)0, bytes, kBufferFlags);
-            r0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0));
-            r1 = __builtin_bit_cast(float4,
-                                    __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16, 0, 0));
-        };
         auto factors = [&](const float4 &r0, float (&a)[RB], float &g) {
 #pragma unroll
             for (int b = 0; b < RB; ++b) {
@@ -720,6 +727,15 @@ __device__ __forceinline__ void field_body(
             }
             const float dx = zcol - r0.x;
             g = fast_exp2(nal2 * dx * dx);
+        };
+        auto load = [&](int j0, float4 &r0, float4 &r1) {
+            const int jj = __builtin_amdgcn_readfirstlane(min(j0, n_in));
+            const int bytes = __builtin_amdgcn_readfirstlane((n_in - jj) * 32);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(packed + 2 * jj), (short)0, bytes, kBufferFlags);
+            r0 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0));
+            r1 = __builtin_bit_cast(float4,
+                                    __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16, 0, 0));
         };
         // Ring of kRing record buffers: step u of a group uses buffer u and
         // refills it for the same step of the next group, so every load has
@@ -765,42 +781,46 @@ __device__ __forceinline__ void field_body(
     // of every row block
     const int rbase = ks * kRegsOwned;
     if constexpr (SPLITK > 1) {
-        int slot = 0;
+        {
+            int slot = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if (r >= rbase && r < rbase + kRegsOwned) continue;
+            for (int r = 0; r < 16; ++r) {
+                if (r >= rbase && r < rbase + kRegsOwned) continue;
 #pragma unroll
-            for (int bl = 0; bl < RB; ++bl)
+                for (int bl = 0; bl < RB; ++bl)
 #pragma unroll
-                for (int c = 0; c < 6; ++c)
-                    lds.part[wave][(slot * RB + bl) * 6 + c][lane] = acc[bl][c][r];
-            ++slot;
+                    for (int c = 0; c < 6; ++c)
+                        lds.part[wave][(slot * RB + bl) * 6 + c][lane] = acc[bl][c][r];
+                ++slot;
+            }
         }
         __syncthreads();
-        // add the partials in wavefront order 0, 1, ..., SPLITK-1
-        const int wbase = (wave / SPLITK) * SPLITK;
+        {
+            // add the partials in wavefront order 0, 1, ..., SPLITK-1
+            const int wbase = (wave / SPLITK) * SPLITK;
 #pragma unroll
-        for (int rr = 0; rr < kRegsOwned; ++rr) {
-            const int r = rbase + rr;
+            for (int rr = 0; rr < kRegsOwned; ++rr) {
+                const int r = rbase + rr;
 #pragma unroll
-            for (int bl = 0; bl < RB; ++bl)
+                for (int bl = 0; bl < RB; ++bl)
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    float sum = 0.f;
-                    for (int src = 0; src < SPLITK; ++src) {
-                        float v;
-                        if (src == ks) {
-                            v = acc[bl][c][r];
-                        } else {
-                            // slot of register r in wavefront src's list
-                            const int src_base = src * kRegsOwned;
-                            const int sl = r < src_base ? r : r - kRegsOwned;
-                            v = lds.part[wbase + src][(sl * RB + bl) * 6 + c][lane];
+                    for (int c = 0; c < 6; ++c) {
+                        float sum = 0.f;
+                        for (int src = 0; src < SPLITK; ++src) {
+                            float v;
+                            if (src == ks) {
+                                v = acc[bl][c][r];
+                            } else {
+                                // slot of register r in wavefront src's list
+                                const int src_base = src * kRegsOwned;
+                                const int sl = r < src_base ? r : r - kRegsOwned;
+                                v = lds.part[wbase + src][(sl * RB + bl) * 6 + c][lane];
+                            }
+                            sum = src == 0 ? v : sum + v;
                         }
-                        sum = src == 0 ? v : sum + v;
+                        acc[bl][c][r] = sum;
                     }
-                    acc[bl][c][r] = sum;
-                }
+            }
         }
     }
     if (tile >= n_tiles) return;
@@ -836,6 +856,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(
     field_body<MODE, SPLITK, RB>(packed, st, nal2, zx0, zy0, w, h, tiles_x, n_tiles, out, frame, fw, fh, fpitch, canvas, cpitch, ox, oy, blockIdx.x);
 }
 
+
 // ------------------------------------------- half-precision field / warp ----
 //
 // The same blend with the two GEMM operands in FP16 or BF16 and FP32
@@ -863,6 +884,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(
 // barrier per chunk).
 enum { kDtF16 = 0, kDtBF16 = 1 };
 constexpr int kHTx = 128, kHTy = 64, kHK = 64, kHStride = kHK + 8;   // LDS rows padded
+constexpr int kTabRows = 4096;   // factor-table rows per axis (one slab of the region)
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
@@ -904,7 +926,9 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
     const float4 *__restrict__ packed, const float *__restrict__ xs,
     const float *__restrict__ ys, const DevState *__restrict__ st, float ka, int zx0, int zy0,
     int w, int h, int tiles_x, float2 *__restrict__ out, const uint8_t *__restrict__ frame,
-    int fw, int fh, int fpitch, float4 *__restrict__ canvas, int cpitch, int ox, int oy) {
+    int fw, int fh, int fpitch, float4 *__restrict__ canvas, int cpitch, int ox, int oy,
+    const void *__restrict__ gx_tab, const void *__restrict__ gy_tab, int tab_stride,
+    int opitch) {
     using T = typename HalfT<DT>::T;
     using V8 = typename HalfT<DT>::V8;
     using V4 = typename HalfT<DT>::V4;
@@ -992,24 +1016,36 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
         const int gcol = 64 * (wave & 1) + lane;
         const float zxa = ka * (float)(px0 + gcol), zya = ka * (float)(py0 + lane);
         const int jx = 32 * (wave >> 1), jy = 16 * wave;
+        // With tables (gx_tab set) the factors were computed once per launch
+        // by k_half_tables: rows of tab_stride values per grid column / row
+        // of the region, zero past the inliers.
+        const T *gxt = gx_tab ? (const T *)gx_tab + (size_t)(px0 - zx0 + gcol) * tab_stride
+                              : nullptr;
+        const T *gyt = gy_tab ? (const T *)gy_tab + (size_t)(py0 - zy0 + lane) * tab_stride
+                              : nullptr;
         auto gen = [&](int jc, int nb, int part) {
             const int bx = __builtin_amdgcn_readfirstlane(jc + jx + 8 * part);
             const int by = __builtin_amdgcn_readfirstlane(jc + jy + 4 * part);
             V8 gxv;
+            V4 gyv;
+            if (gxt) {
+                gxv = *(const V8 *)(gxt + bx);
+                gyv = *(const V4 *)(gyt + by);
+            } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float d = ka * xs[bx + i] - zxa;
-                const float e = fast_exp2(-(d * d));
-                gxv[i] = (T)(bx + i < n_in ? e : 0.f);
+                for (int i = 0; i < 8; ++i) {
+                    const float d = ka * xs[bx + i] - zxa;
+                    const float e = fast_exp2(-(d * d));
+                    gxv[i] = (T)(bx + i < n_in ? e : 0.f);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float d = ka * ys[by + i] - zya;
+                    const float e = fast_exp2(-(d * d));
+                    gyv[i] = (T)(by + i < n_in ? e : 0.f);
+                }
             }
             *(V8 *)&L.gx[nb][gcol][jx + 8 * part] = gxv;
-            V4 gyv;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float d = ka * ys[by + i] - zya;
-                const float e = fast_exp2(-(d * d));
-                gyv[i] = (T)(by + i < n_in ? e : 0.f);
-            }
             *(V4 *)&L.gy[nb][lane][jy + 4 * part] = gyv;
             if (part == 0 && wave == 3) {
                 const int j = jc + lane;
@@ -1062,18 +1098,75 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
                 }
             }
         };
+        if (gxt) {
+            // Tables: the next chunk's factors and node records are loaded
+            // into registers one chunk ahead and stored to LDS after the
+            // current chunk's MFMAs, so the loads' latency is hidden.
+            V8 pgx[4];
+            V4 pgy[4];
+            float4 pr0 = make_float4(0.f, 0.f, 0.f, 0.f), pr1 = pr0;
+            auto fetch = [&](int jc) {
 #pragma unroll
-        for (int part = 0; part < 4; ++part) gen(0, 0, part);
-        __syncthreads();
-        for (int c = 0; c < nchunks; ++c) {
-            const int buf = c & 1;
-            const bool more = c + 1 < nchunks;
+                for (int part = 0; part < 4; ++part) {
+                    const int bx = __builtin_amdgcn_readfirstlane(jc + jx + 8 * part);
+                    const int by = __builtin_amdgcn_readfirstlane(jc + jy + 4 * part);
+                    pgx[part] = *(const V8 *)(gxt + bx);
+                    pgy[part] = *(const V4 *)(gyt + by);
+                }
+                if (wave == 3 && jc + lane < n_in) {
+                    pr0 = packed[2 * (jc + lane)];
+                    pr1 = packed[2 * (jc + lane) + 1];
+                }
+            };
+            auto store = [&](int jc, int nb) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                kstep(buf, s);
-                if (more) gen((c + 1) * kHK, buf ^ 1, s);
-            }
+                for (int part = 0; part < 4; ++part) {
+                    *(V8 *)&L.gx[nb][gcol][jx + 8 * part] = pgx[part];
+                    *(V4 *)&L.gy[nb][lane][jy + 4 * part] = pgy[part];
+                }
+                if (wave == 3) {
+                    float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (jc + lane < n_in) {
+                        const float4 qj = make_float4(1.f + pr0.z, pr0.w, pr1.x, pr1.y);
+                        const float4 qc = dq_mul(dq_mul(aq, qj), bq);
+                        v[0] = ch0m1 + ch0 * pr0.z + sh0 * pr0.w;   // q'_c - 1
+                        v[1] = qc.y;
+                        v[2] = qc.z;
+                        v[3] = qc.w;
+                        v[4] = pr1.z - sm1;                           // s_j - s0
+                    }
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) L.qd[nb][c][lane] = (typename HalfT<DT>::Q)v[c];
+                }
+            };
+            fetch(0);
+            store(0, 0);
+            if (nchunks > 1) fetch(kHK);
             __syncthreads();
+            for (int c = 0; c < nchunks; ++c) {
+                const int buf = c & 1;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) kstep(buf, s);
+                if (c + 1 < nchunks) {
+                    store((c + 1) * kHK, buf ^ 1);
+                    if (c + 2 < nchunks) fetch((c + 2) * kHK);
+                }
+                __syncthreads();
+            }
+        } else {
+#pragma unroll
+            for (int part = 0; part < 4; ++part) gen(0, 0, part);
+            __syncthreads();
+            for (int c = 0; c < nchunks; ++c) {
+                const int buf = c & 1;
+                const bool more = c + 1 < nchunks;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    kstep(buf, s);
+                    if (more) gen((c + 1) * kHK, buf ^ 1, s);
+                }
+                __syncthreads();
+            }
         }
     }
 
@@ -1099,13 +1192,48 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
         const float fzx = (float)zx, fzy = (float)zy;
         const float2 d = make_float2(ex + sg * (fzx + ex), ey + sg * (fzy + ey));
         if constexpr (MODE == kModeField) {
-            out[(size_t)(zy - zy0) * w + (zx - zx0)] =
+            out[(size_t)(zy - zy0) * opitch + (zx - zx0)] =
                 bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
                     : make_float2(fzx + d.x, fzy + d.y);
         } else {
             warp_merge(zx, zy, d, frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
         }
     }
+}
+
+// Per-axis Gaussian factors of the half-precision blend, once per launch:
+// row c of the x table holds gx(zx0 + c, j) = exp(-alpha (zx0 + c - x_j)^2)
+// for j < tab_stride (zero for j >= n_in), row r of the y table likewise for
+// zy0 + r.  One thread writes eight consecutive j of one row.
+template <int DT>
+__global__ __launch_bounds__(256) void k_half_tables(
+    const float *__restrict__ xs, const float *__restrict__ ys,
+    const DevState *__restrict__ st, float ka, int zx0, int zy0, int rows_x, int rows_y,
+    int tab_stride, void *__restrict__ gx_tab, void *__restrict__ gy_tab) {
+    using T = typename HalfT<DT>::T;
+    using V8 = typename HalfT<DT>::V8;
+    const int n_in = st->status < 0 ? 0 : st->n_in;
+    const int per_row = tab_stride / 8;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)(rows_x + rows_y) * per_row) return;
+    const int row = (int)(e / per_row), j0 = 8 * (int)(e % per_row);
+    const bool is_x = row < rows_x;
+    const int r = is_x ? row : row - rows_x;
+    const float za = ka * (float)(is_x ? zx0 + r : zy0 + r);
+    const float *src = is_x ? xs : ys;
+    V8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int j = j0 + i;
+        float g = 0.f;
+        if (j < n_in) {
+            const float d = ka * src[j] - za;
+            g = fast_exp2(-(d * d));
+        }
+        v[i] = (T)g;
+    }
+    T *dst = (T *)(is_x ? gx_tab : gy_tab) + (size_t)r * tab_stride + j0;
+    *(V8 *)dst = v;
 }
 
 // ---------------------------------------------- node tracking, uncertainty ----
@@ -1292,31 +1420,35 @@ __device__ __forceinline__ double dist2_f64(float2 a, float2 b) {
     return dx * dx + dy * dy;   // rounded as written, no fused multiply-add
 }
 
-// LDS written by some lanes of a wavefront and read by others of the same
-// wavefront: keep the compiler from moving accesses across this point.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
-__global__ __launch_bounds__(kStartThreads) void k_start(
-    const float2 *__restrict__ src, const float2 *__restrict__ dst, int n, float g,
-    const float *__restrict__ wts, float *__restrict__ p_out) {
+// With feat_out set, the features are written out ([n][64]) and the network
+// is not evaluated (wts and p_out unused).
+__device__ __forceinline__ void start_body(const float2 *__restrict__ src,
+                                           const float2 *__restrict__ dst, int n, float g,
+                                           const float *__restrict__ wts,
+                                           float *__restrict__ p_out,
+                                           float *__restrict__ feat_out, int block,
+                                           int nblocks) {
     __shared__ StartLds L;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
-    const float *W1 = wts, *B1 = W1 + kNHid * kNFeat, *W2 = B1 + kNHid;
-    const float *B2 = W2 + kNHid * kNHid, *W3 = B2 + kNHid, *B3 = W3 + kNHid;
-    for (int t = tid; t < kNHid * kNFeat; t += kStartThreads) L.w1t[t % kNFeat][t / kNFeat] = W1[t];
-    for (int t = tid; t < kNHid * kNHid; t += kStartThreads) L.w2t[t % kNHid][t / kNHid] = W2[t];
-    for (int t = tid; t < kNHid; t += kStartThreads) {
-        L.b1[t] = B1[t];
-        L.b2[t] = B2[t];
-        L.w3[t] = W3[t];
+    float b3 = 0.f;
+    if (!feat_out) {
+        const float *W1 = wts, *B1 = W1 + kNHid * kNFeat, *W2 = B1 + kNHid;
+        const float *B2 = W2 + kNHid * kNHid, *W3 = B2 + kNHid, *B3 = W3 + kNHid;
+        for (int t = tid; t < kNHid * kNFeat; t += kStartThreads)
+            L.w1t[t % kNFeat][t / kNFeat] = W1[t];
+        for (int t = tid; t < kNHid * kNHid; t += kStartThreads)
+            L.w2t[t % kNHid][t / kNHid] = W2[t];
+        for (int t = tid; t < kNHid; t += kStartThreads) {
+            L.b1[t] = B1[t];
+            L.b2[t] = B2[t];
+            L.w3[t] = W3[t];
+        }
+        b3 = B3[0];
+        __syncthreads();
     }
-    const float b3 = B3[0];
-    __syncthreads();
 
-    for (int i = blockIdx.x * kStartWaves + wave; i < n; i += gridDim.x * kStartWaves) {
+    for (int i = block * kStartWaves + wave; i < n; i += nblocks * kStartWaves) {
         const float2 xi = src[i];
         // ---- per-lane sorted lists of the 16 nearest (lanes scan j in
         // increasing order, so an equal distance never displaces an entry)
@@ -1367,7 +1499,9 @@ __global__ __launch_bounds__(kStartThreads) void k_start(
                                  ey / (1.f + fabsf(ey)));
             }
             *(float4 *)&L.f[wave][4 * lane] = fv;
+            if (feat_out) *(float4 *)&feat_out[(size_t)i * kNFeat + 4 * lane] = fv;
         }
+        if (feat_out) continue;
         wave_sync();   // features are per wavefront: no workgroup barrier
         // layer 1
         float a0 = L.b1[lane], a1 = L.b1[lane + 64];
@@ -1394,13 +1528,40 @@ __global__ __launch_bounds__(kStartThreads) void k_start(
     }
 }
 
+__global__ __launch_bounds__(kStartThreads) void k_start(
+    const float2 *__restrict__ src, const float2 *__restrict__ dst, int n, float g,
+    const float *__restrict__ wts, float *__restrict__ p_out) {
+    start_body(src, dst, n, g, wts, p_out, nullptr, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kStartThreads) void k_start_features(
+    const float2 *__restrict__ src, const float2 *__restrict__ dst, int n, float g,
+    float *__restrict__ feat_out) {
+    start_body(src, dst, n, g, nullptr, nullptr, feat_out, blockIdx.x, gridDim.x);
+}
+
+struct StartJob {
+    const float2 *src, *dst;
+    float *p_out;
+    int n;
+    float g;
+};
+
+// One launch for many pairs: blockIdx.y = pair, the pair's matches strided
+// over the gridDim.x workgroups.
+__global__ __launch_bounds__(kStartThreads) void k_start_b(const StartJob *__restrict__ jobs,
+                                                           const float *__restrict__ wts) {
+    const StartJob &J = jobs[blockIdx.y];
+    start_body(J.src, J.dst, J.n, J.g, wts, J.p_out, nullptr, blockIdx.x, gridDim.x);
+}
+
 // EM start from given posteriors: xy as k_load, p = init_p, mask = p > thresh
 // (FP32); a non-finite start or coordinate sets ENONFINITE.
-__global__ void k_load_from(const float2 *__restrict__ src, const float2 *__restrict__ dst,
-                            const float *__restrict__ init_p, int n, float p_thresh,
-                            float4 *__restrict__ xy, float *__restrict__ p,
-                            uint8_t *__restrict__ mask, DevState *st) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void load_from_body(
+    const float2 *__restrict__ src, const float2 *__restrict__ dst,
+    const float *__restrict__ init_p, int n, float p_thresh, float4 *__restrict__ xy,
+    float *__restrict__ p, uint8_t *__restrict__ mask, DevState *st, int block) {
+    const int i = block * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float2 a = src[i], b = dst[i];
     const float pi = init_p[i];
@@ -1411,6 +1572,148 @@ __global__ void k_load_from(const float2 *__restrict__ src, const float2 *__rest
         atomicMin(&st->status, (int)EMDQ_ENONFINITE);
         atomicExch(&st->done, 1);
     }
+}
+
+__global__ void k_load_from(const float2 *__restrict__ src, const float2 *__restrict__ dst,
+                            const float *__restrict__ init_p, int n, float p_thresh,
+                            float4 *__restrict__ xy, float *__restrict__ p,
+                            uint8_t *__restrict__ mask, DevState *st) {
+    load_from_body(src, dst, init_p, n, p_thresh, xy, p, mask, st, blockIdx.x);
+}
+
+
+// ------------------------------------------------- learned start: training ----
+//
+// One Adam step of the learned start's network on a minibatch (mean binary
+// cross-entropy; label 1 = inlier).  k_start_grad: workgroup gi takes the
+// samples idx[gi], idx[gi + G], ... in that order, one at a time, all 256
+// threads on one sample: thread t = (o, h) = (t / 2, t % 2) owns row o of W1
+// (columns [32 h, 32 h + 32), kept in registers) and of W2 (columns
+// [64 h, 64 h + 64)) and accumulates their gradients in registers; W2 sits
+// in LDS with padded rows so that both its rows (forward) and its columns
+// (backward) read without bank conflicts.  Each workgroup writes its partial
+// gradient (and loss) to its own slot of the workspace; k_start_adam adds
+// the slots in workgroup order, so a step is deterministic.
+constexpr int kTrainThreads = 256;
+constexpr int kNW = kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid + kNHid + 1;
+constexpr int kOffB1 = kNHid * kNFeat, kOffW2 = kOffB1 + kNHid, kOffB2 = kOffW2 + kNHid * kNHid;
+constexpr int kOffW3 = kOffB2 + kNHid, kOffB3 = kOffW3 + kNHid;
+constexpr int kSlot = kNW + 1;   // a workgroup's partial gradient, then its loss
+
+__device__ __forceinline__ float gelu_grad(float t) {
+    return 0.5f * (1.f + erff(t * 0.70710678118654752f)) +
+           t * 0.39894228040143268f * expf(-0.5f * t * t);
+}
+
+__global__ __launch_bounds__(kTrainThreads) void k_start_grad(
+    const float *__restrict__ wts, const float *__restrict__ feat,
+    const float *__restrict__ label, const int *__restrict__ idx, int batch, int m_samples,
+    float *__restrict__ work) {
+    __shared__ float w2[kNHid][kNHid + 1];
+    __shared__ float fL[kNFeat], a1L[kNHid], h1L[kNHid], d2L[kNHid], red[kTrainThreads / kWave];
+    const int t = threadIdx.x, o = t >> 1, h = t & 1, lane = t & (kWave - 1), wave = t >> 6;
+    const int G = gridDim.x, gi = blockIdx.x;
+    for (int e = t; e < kNHid * kNHid; e += kTrainThreads) w2[e / kNHid][e % kNHid] = wts[kOffW2 + e];
+    float w1r[32], gw1[32], gw2[64];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        w1r[k] = wts[o * kNFeat + 32 * h + k];
+        gw1[k] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 64; ++k) gw2[k] = 0.f;
+    const float b1 = wts[kOffB1 + o], b2 = wts[kOffB2 + o], w3 = wts[kOffW3 + o];
+    const float b3 = wts[kOffB3];
+    float gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f, loss = 0.f;
+    __syncthreads();
+    for (int sidx = gi; sidx < batch; sidx += G) {
+        const int sm = idx[sidx];
+        if (sm < 0 || sm >= m_samples) continue;   // uniform: the whole workgroup skips it
+        if (t < kNFeat) fL[t] = feat[(size_t)sm * kNFeat + t];
+        const float y = label[sm];
+        __syncthreads();
+        // layer 1: a1[o] from the two halves of row o
+        float p = 0.f;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) p = fmaf(w1r[k], fL[32 * h + k], p);
+        p += __shfl_xor(p, 1, kWave);
+        const float a1 = p + b1;
+        if (h == 0) {
+            a1L[o] = a1;
+            h1L[o] = gelu(a1);
+        }
+        __syncthreads();
+        // layer 2
+        float q = 0.f;
+#pragma unroll 16
+        for (int k = 0; k < 64; ++k) q = fmaf(w2[o][64 * h + k], h1L[64 * h + k], q);
+        q += __shfl_xor(q, 1, kWave);
+        const float a2 = q + b2, h2 = gelu(a2);
+        float zc = h == 0 ? w3 * h2 : 0.f;
+        zc = wave_sum(zc);
+        if (lane == 0) red[wave] = zc;
+        __syncthreads();
+        const float z = ((red[0] + red[1]) + red[2]) + red[3] + b3;
+        const float dz = 1.f / (1.f + expf(-z)) - y;
+        if (t == 0) {
+            loss += (z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z))) - y * z;
+            gb3 += dz;
+        }
+        const float d2 = dz * w3 * gelu_grad(a2);
+        if (h == 0) {
+            gw3 += dz * h2;
+            gb2 += d2;
+            d2L[o] = d2;
+        }
+#pragma unroll
+        for (int k = 0; k < 64; ++k) gw2[k] = fmaf(d2, h1L[64 * h + k], gw2[k]);
+        __syncthreads();
+        // back through W2: column o, rows of this thread's half
+        float s = 0.f;
+#pragma unroll 16
+        for (int r = 0; r < 64; ++r) s = fmaf(w2[64 * h + r][o], d2L[64 * h + r], s);
+        s += __shfl_xor(s, 1, kWave);
+        const float d1 = s * gelu_grad(a1L[o]);
+        if (h == 0) gb1 += d1;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) gw1[k] = fmaf(d1, fL[32 * h + k], gw1[k]);
+        __syncthreads();   // the next sample overwrites the LDS rows
+    }
+    float *slot = work + (size_t)gi * kSlot;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) slot[o * kNFeat + 32 * h + k] = gw1[k];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) slot[kOffW2 + o * kNHid + 64 * h + k] = gw2[k];
+    if (h == 0) {
+        slot[kOffB1 + o] = gb1;
+        slot[kOffB2 + o] = gb2;
+        slot[kOffW3 + o] = gw3;
+    }
+    if (t == 0) {
+        slot[kOffB3] = gb3;
+        slot[kNW] = loss;
+    }
+}
+
+// Sums the G slots in order (mean over the batch), stores the gradient and
+// the mean loss after the last slot, and applies Adam (step t >= 1).
+__global__ void k_start_adam(float *__restrict__ wts, float *__restrict__ m1,
+                             float *__restrict__ m2, float *__restrict__ work, int G, int batch,
+                             float lr, float beta1, float beta2, float eps, int step) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > kNW) return;
+    float sum = 0.f;
+    for (int gi = 0; gi < G; ++gi) sum += work[(size_t)gi * kSlot + k];
+    const float gk = sum / (float)batch;
+    work[(size_t)G * kSlot + k] = gk;   // k == kNW: the mean loss
+    if (k == kNW) return;
+    const float a = beta1 * m1[k] + (1.f - beta1) * gk;
+    const float b = beta2 * m2[k] + (1.f - beta2) * gk * gk;
+    m1[k] = a;
+    m2[k] = b;
+    const float ah = a / (1.f - powf(beta1, (float)step));
+    const float bh = b / (1.f - powf(beta2, (float)step));
+    wts[k] -= lr * ah / (sqrtf(bh) + eps);
 }
 
 constexpr int kSplitK = EMDQ_SPLITK;
@@ -1429,6 +1732,7 @@ constexpr int kRowBlocks = EMDQ_ROWBLOCKS;
 // workgroup finding its pair by a binary search of the tile offsets.
 struct EmJob {
     const float2 *src, *dst;
+    const float *init_p;   // null: the plain start p = 1
     float4 *xy;
     float *p;
     uint8_t *mask;
@@ -1458,10 +1762,14 @@ __global__ void k_reset_b(const EmJob *__restrict__ jobs) {
     if (threadIdx.x == 0) reset_state(jobs[blockIdx.x].st);
 }
 
-__global__ void k_load_b(const EmJob *__restrict__ jobs) {
+__global__ void k_load_b(const EmJob *__restrict__ jobs, float p_thresh) {
     const EmJob &J = jobs[blockIdx.y];
     if ((int)blockIdx.x * (int)blockDim.x >= J.n) return;
-    load_body(J.src, J.dst, J.n, J.xy, J.p, J.mask, J.st, blockIdx.x);
+    if (J.init_p)
+        load_from_body(J.src, J.dst, J.init_p, J.n, p_thresh, J.xy, J.p, J.mask, J.st,
+                       blockIdx.x);
+    else
+        load_body(J.src, J.dst, J.n, J.xy, J.p, J.mask, J.st, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kEmThreads) void k_mstep_b(const EmJob *__restrict__ jobs,
@@ -1496,7 +1804,7 @@ __global__ void k_gather_states(const EmJob *__restrict__ jobs, int n_pairs,
     if (i < n_pairs) out[i] = *jobs[i].st;
 }
 
-template <int MODE>
+template <int MODE, int SPLITK>
 __global__ __launch_bounds__(kFieldThreads) void k_field_b(const FieldJob *__restrict__ jobs,
                                                            int n_jobs) {
     int lo = 0, hi = n_jobs - 1;   // last job whose first workgroup is <= blockIdx.x
@@ -1505,7 +1813,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_b(const FieldJob *__res
         if (jobs[mid].block_base <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
     }
     const FieldJob &J = jobs[lo];
-    field_body<MODE, kSplitK, kRowBlocks>(J.packed, J.st, J.nal2, J.zx0, J.zy0, J.w, J.h,
+    field_body<MODE, SPLITK, kRowBlocks>(J.packed, J.st, J.nal2, J.zx0, J.zy0, J.w, J.h,
                                           J.tiles_x, J.n_tiles, J.out, J.frame, J.fw, J.fh,
                                           J.fpitch, J.canvas, J.cpitch, J.ox, J.oy,
                                           (int)blockIdx.x - J.block_base);
@@ -1530,8 +1838,12 @@ struct emdq_model_s {
     float *xs = nullptr;     // inlier coordinates, SoA, padded by one chunk
     float *ys = nullptr;
     int precision = EMDQ_PREC_F32;
+    void *half_tab = nullptr;   // x and y factor tables of the half-precision blend
+    int tab_stride = 0;         // values per table row: n_max rounded up to 64
     DevState *st = nullptr;
     DevState *host_st = nullptr;   // pinned
+    DevState *em_st = nullptr;     // pinned [2]: stop flags read while the EM runs on
+    hipEvent_t em_ev[2] = {};
     hipStream_t last = nullptr;
 };
 
@@ -1572,22 +1884,47 @@ emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h,
     const long long blocks = (n_tiles + tiles_per_wg - 1) / tiles_per_wg;
     if (blocks > 0x7fffffffLL / kFieldThreads) return EMDQ_EINVAL;
     if (m->precision != EMDQ_PREC_F32) {
-        const long long hx = (w + kHTx - 1) / kHTx, hy = (h + kHTy - 1) / kHTy;
-        if (hx * hy > 0x7fffffffLL) return EMDQ_EINVAL;
-        const unsigned nb = (unsigned)(hx * hy);
+        // Slabs of at most kTabRows columns and rows, each with its factor
+        // tables computed first (the tables hold one slab).
         const float ka = sqrtf(m->alpha * kLog2e);
         const bool f16 = m->precision == EMDQ_PREC_F16;
-        if (mode == kModeField) {
-            auto k = f16 ? k_field_half<kModeField, kDtF16> : k_field_half<kModeField, kDtBF16>;
-            hipLaunchKernelGGL(k, dim3(nb), dim3(kFieldThreads), 0, stream, m->packed, m->xs,
-                               m->ys, m->st, ka, zx0, zy0, w, h, (int)hx, out, nullptr, 0, 0,
-                               0, nullptr, 0, 0, 0);
-        } else {
-            auto k = f16 ? k_field_half<kModeWarp, kDtF16> : k_field_half<kModeWarp, kDtBF16>;
-            hipLaunchKernelGGL(k, dim3(nb), dim3(kFieldThreads), 0, stream, m->packed, m->xs,
-                               m->ys, m->st, ka, zx0, zy0, w, h, (int)hx, nullptr, frame, fw, fh,
-                               fpitch, canvas, cpitch, ox, oy);
-        }
+        void *gxt = m->half_tab;
+        void *gyt = m->half_tab ? (char *)m->half_tab + (size_t)kTabRows * m->tab_stride * 2 : nullptr;
+        for (int sy = 0; sy < h; sy += kTabRows)
+            for (int sx = 0; sx < w; sx += kTabRows) {
+                const int sw = min(kTabRows, w - sx), sh = min(kTabRows, h - sy);
+                const int hx = (sw + kHTx - 1) / kHTx, hy = (sh + kHTy - 1) / kHTy;
+                const int zx = zx0 + sx, zy = zy0 + sy;
+                if (gxt) {
+                    const long long elems = (long long)(hx * kHTx + hy * kHTy) * (m->tab_stride / 8);
+                    const unsigned tb = (unsigned)((elems + 255) / 256);
+                    if (f16)
+                        hipLaunchKernelGGL(k_half_tables<kDtF16>, dim3(tb), dim3(256), 0, stream,
+                                           m->xs, m->ys, m->st, ka, zx, zy, hx * kHTx,
+                                           hy * kHTy, m->tab_stride, gxt, gyt);
+                    else
+                        hipLaunchKernelGGL(k_half_tables<kDtBF16>, dim3(tb), dim3(256), 0,
+                                           stream, m->xs, m->ys, m->st, ka, zx, zy, hx * kHTx,
+                                           hy * kHTy, m->tab_stride, gxt, gyt);
+                }
+                // the slab's outputs are addressed through its own origin
+                const unsigned nb = (unsigned)(hx * hy);
+                if (mode == kModeField) {
+                    auto k = f16 ? k_field_half<kModeField, kDtF16>
+                                 : k_field_half<kModeField, kDtBF16>;
+                    hipLaunchKernelGGL(k, dim3(nb), dim3(kFieldThreads), 0, stream, m->packed,
+                                       m->xs, m->ys, m->st, ka, zx, zy, sw, sh, hx,
+                                       out + (size_t)sy * w + sx, nullptr, 0, 0, 0, nullptr, 0, 0,
+                                       0, gxt, gyt, m->tab_stride, w);
+                } else {
+                    auto k = f16 ? k_field_half<kModeWarp, kDtF16>
+                                 : k_field_half<kModeWarp, kDtBF16>;
+                    hipLaunchKernelGGL(k, dim3(nb), dim3(kFieldThreads), 0, stream, m->packed,
+                                       m->xs, m->ys, m->st, ka, zx, zy, sw, sh, hx, nullptr,
+                                       frame, fw, fh, fpitch, canvas, cpitch, ox, oy, gxt, gyt,
+                                       m->tab_stride, w);
+                }
+            }
         return check_launch();
     }
     const float nal2 = -m->alpha * kLog2e;
@@ -1664,6 +2001,10 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     ok = ok && hipMalloc((void **)&m->st, sizeof(DevState)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&m->host_st, sizeof(DevState), hipHostMallocDefault) ==
                    hipSuccess;
+    ok = ok && hipHostMalloc((void **)&m->em_st, 2 * sizeof(DevState), hipHostMallocDefault) ==
+                   hipSuccess;
+    for (int k = 0; ok && k < 2; ++k)
+        ok = hipEventCreateWithFlags(&m->em_ev[k], hipEventDisableTiming) == hipSuccess;
     if (ok) {
         // an empty model: status ENOINLIERS until a fit or set_nodes
         DevState init = {};
@@ -1690,8 +2031,12 @@ void emdq_model_free(emdq_model m) {
     (void)hipFree(m->packed);
     (void)hipFree(m->xs);
     (void)hipFree(m->ys);
+    (void)hipFree(m->half_tab);
     (void)hipFree(m->st);
     if (m->host_st) (void)hipHostFree(m->host_st);
+    if (m->em_st) (void)hipHostFree(m->em_st);
+    for (int k = 0; k < 2; ++k)
+        if (m->em_ev[k]) (void)hipEventDestroy(m->em_ev[k]);
     delete m;
 }
 
@@ -1732,14 +2077,18 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
                            (const float2 *)src_xy, (const float2 *)dst_xy, n, m->xy, m->p,
                            m->mask, m->st);
     if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
+    auto mstep = [&](int final_pass) {
+        hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy, m->p,
+                           n, nal2, alpha, m->q, m->s, m->st, final_pass);
+    };
     // EM: iterations are enqueued in chunks; every kernel returns at once
-    // after the device-side stop flag is set, so a chunk may overshoot.
+    // after the device-side stop flag is set, so a chunk may overshoot.  The
+    // stop flag after chunk k is read while chunk k + 1 already runs, so the
+    // GPU does not wait for the host between chunks.
     int enqueued = 0;
-    const int chunk = 4;
-    while (true) {
-        for (int c = 0; c < chunk && enqueued < prm.max_iter; ++c, ++enqueued) {
-            hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
-                               m->p, n, nal2, alpha, m->q, m->s, m->st, 0);
+    for (int k = 0;; ++k) {
+        for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
+            mstep(0);
             hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
                                m->p, m->q, m->s, n, nal2, m->e2, m->st);
             hipLaunchKernelGGL(k_posterior, dim3(1), dim3(kPostThreads), 0, stream, m->p, m->e2,
@@ -1747,14 +2096,18 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
                                (double)prm.gamma_max, prm.p_thresh, prm.max_iter, m->st);
         }
         if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
-        EMDQ_HIP(hipMemcpyAsync(m->host_st, m->st, sizeof(DevState), hipMemcpyDeviceToHost,
-                                stream));
-        EMDQ_HIP(hipStreamSynchronize(stream));
-        if (m->host_st->done || m->host_st->status < 0 || enqueued >= prm.max_iter) break;
+        EMDQ_HIP(hipMemcpyAsync(&m->em_st[k & 1], m->st, sizeof(DevState),
+                                hipMemcpyDeviceToHost, stream));
+        EMDQ_HIP(hipEventRecord(m->em_ev[k & 1], stream));
+        if (k > 0) {
+            EMDQ_HIP(hipEventSynchronize(m->em_ev[(k - 1) & 1]));
+            const DevState &prev = m->em_st[(k - 1) & 1];
+            if (prev.done || prev.status < 0) break;
+        }
+        if (enqueued >= prm.max_iter) break;
     }
     // final fit with the final posteriors, then pack the inliers
-    hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy, m->p, n,
-                       nal2, alpha, m->q, m->s, m->st, 1);
+    mstep(1);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, stream, m->xy, m->q,
                        m->s, m->mask, n, m->packed, m->xs, m->ys, m->st);
     return check_launch();
@@ -1874,6 +2227,42 @@ emdq_status emdq_learned_start(const float *src_xy, const float *dst_xy, int n, 
     return check_launch();
 }
 
+emdq_status emdq_start_features(const float *src_xy, const float *dst_xy, int n, int frame_w,
+                                int frame_h, const emdq_params *params, float *feat_out,
+                                hipStream_t stream) {
+    if (!src_xy || !dst_xy || !feat_out || frame_w <= 0 || frame_h <= 0) return EMDQ_EINVAL;
+    if (n < 2) return EMDQ_ETOOFEW;
+    emdq_params prm;
+    if (params) prm = *params; else emdq_params_default(&prm);
+    if (!params_ok(prm)) return EMDQ_EINVAL;
+    const float g = (float)sqrt(alpha_d(prm, frame_w, frame_h));
+    int blocks = (n + kStartWaves - 1) / kStartWaves;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_start_features, dim3((unsigned)blocks), dim3(kStartThreads), 0, stream,
+                       (const float2 *)src_xy, (const float2 *)dst_xy, n, g, feat_out);
+    return check_launch();
+}
+
+size_t emdq_start_train_work_floats(int groups) {
+    if (groups < 1) return 0;
+    return (size_t)(groups + 1) * (size_t)kSlot;
+}
+
+emdq_status emdq_start_train_step(float *weights, float *adam_m, float *adam_v, int step,
+                                  const float *feat, const float *label, int m_samples,
+                                  const int *idx, int batch, float lr, int groups, float *work,
+                                  hipStream_t stream) {
+    if (!weights || !adam_m || !adam_v || !feat || !label || !idx || !work) return EMDQ_EINVAL;
+    if (m_samples < 1 || batch < 1 || step < 1 || groups < 1 || groups > 4096 || !(lr > 0.f))
+        return EMDQ_EINVAL;
+    if (groups > batch) groups = batch;
+    hipLaunchKernelGGL(k_start_grad, dim3((unsigned)groups), dim3(kTrainThreads), 0, stream,
+                       weights, feat, label, idx, batch, m_samples, work);
+    hipLaunchKernelGGL(k_start_adam, dim3((kNW + 1 + 255) / 256), dim3(256), 0, stream, weights,
+                       adam_m, adam_v, work, groups, batch, lr, 0.9f, 0.999f, 1e-8f, step);
+    return check_launch();
+}
+
 emdq_status emdq_fit_from(emdq_model m, const float *src_xy, const float *dst_xy, int n,
                           int frame_w, int frame_h, const emdq_params *params,
                           const float *init_p, hipStream_t stream) {
@@ -1886,6 +2275,20 @@ emdq_status emdq_model_set_precision(emdq_model m, emdq_precision precision) {
     if (precision != EMDQ_PREC_F32 && precision != EMDQ_PREC_F16 &&
         precision != EMDQ_PREC_BF16)
         return EMDQ_EINVAL;
+    if (EMDQ_HALF_TABLES && precision != EMDQ_PREC_F32 && !m->half_tab) {
+        const int stride = (m->n_max + 63) / 64 * 64;
+        const size_t bytes = (size_t)2 * kTabRows * (size_t)stride * 2;
+        int prev = 0;
+        if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(m->device) != hipSuccess)
+            return EMDQ_EHIP;
+        const hipError_t e = hipMalloc(&m->half_tab, bytes);
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess) {
+            m->half_tab = nullptr;
+            return EMDQ_ENOMEM;
+        }
+        m->tab_stride = stride;
+    }
     m->precision = precision;
     return EMDQ_OK;
 }
@@ -1924,8 +2327,14 @@ struct emdq_batch_s {
     int max_pairs = 0;
     EmJob *em_jobs = nullptr;        // device
     FieldJob *field_jobs = nullptr;  // device
+    StartJob *start_jobs = nullptr;  // device
+    FieldJob *prepared = nullptr;    // device: the table of emdq_batch_prepare
+    int variant = 0;                 // field-kernel shape (autotuner)
+    int prep_mode = -1, prep_pairs = 0, prep_variant = 0;
+    long long prep_blocks = 0;
     DevState *states = nullptr;      // device, gathered per chunk
-    DevState *host_states = nullptr; // pinned
+    DevState *host_states = nullptr; // pinned, two sets (read while the EM runs on)
+    hipEvent_t em_ev[2] = {};
     static constexpr int kSlots = 4; // pinned staging ring for the job tables
     void *stage[kSlots] = {};
     hipEvent_t stage_done[kSlots] = {};
@@ -1935,8 +2344,10 @@ struct emdq_batch_s {
 namespace {
 
 size_t batch_stage_bytes(int max_pairs) {
-    const size_t a = sizeof(EmJob), b = sizeof(FieldJob);
-    return (a > b ? a : b) * (size_t)max_pairs;
+    size_t a = sizeof(EmJob);
+    if (sizeof(FieldJob) > a) a = sizeof(FieldJob);
+    if (sizeof(StartJob) > a) a = sizeof(StartJob);
+    return a * (size_t)max_pairs;
 }
 
 // A staging slot whose previous upload has completed.
@@ -1971,23 +2382,34 @@ emdq_status batch_region_ok(const emdq_region &r, int mode) {
     return EMDQ_OK;
 }
 
-emdq_status batch_field_launch(emdq_batch b, int n_pairs, const emdq_model *models,
-                               const emdq_region *regions, int mode, hipStream_t stream) {
-    if (!b || !models || !regions || n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
-    for (int i = 0; i < n_pairs; ++i) {
-        if (!models[i]) return EMDQ_EINVAL;
-        const emdq_status rc = batch_region_ok(regions[i], mode);
-        if (rc != EMDQ_OK) return rc;
+// Field-kernel shapes the batched launch can use (split-K 4: one 32 x 32 tile
+// per workgroup of four wavefronts; 2: two tiles; 1: four tiles).
+constexpr int kBatchVariants = 3;
+constexpr int kVariantSplitK[kBatchVariants] = {4, 2, 1};
+
+// Job table of a batched field / warp launch, the pairs ordered by match
+// count (largest first), so the most expensive tiles are dispatched first.
+emdq_status fill_field_jobs(FieldJob *jobs, int n_pairs, const emdq_model *models,
+                            const emdq_region *regions, int splitk, long long *blocks_out) {
+    int *order = (int *)malloc(sizeof(int) * (size_t)n_pairs);
+    if (!order) return EMDQ_ENOMEM;
+    for (int i = 0; i < n_pairs; ++i) order[i] = i;
+    for (int i = 1; i < n_pairs; ++i) {   // stable insertion sort by n, descending
+        const int v = order[i];
+        int k = i;
+        while (k > 0 && models[order[k - 1]]->n < models[v]->n) {
+            order[k] = order[k - 1];
+            --k;
+        }
+        order[k] = v;
     }
-    int slot = 0;
-    FieldJob *jobs = (FieldJob *)batch_slot(b, &slot);
-    if (!jobs) return EMDQ_EHIP;
-    constexpr int tiles_per_wg = 4 / kSplitK;
+    const int tiles_per_wg = 4 / splitk;
     long long base = 0;
-    for (int i = 0; i < n_pairs; ++i) {
+    for (int q = 0; q < n_pairs; ++q) {
+        const int i = order[q];
         const emdq_region &r = regions[i];
         emdq_model m = models[i];
-        FieldJob &J = jobs[i];
+        FieldJob &J = jobs[q];
         const int tiles_x = (r.w + kTile - 1) / kTile;
         const int tiles_y = (r.h + kTile * kRowBlocks - 1) / (kTile * kRowBlocks);
         const long long n_tiles = (r.w && r.h) ? (long long)tiles_x * tiles_y : 0;
@@ -2011,20 +2433,77 @@ emdq_status batch_field_launch(emdq_batch b, int n_pairs, const emdq_model *mode
         J.ox = r.ox;
         J.oy = r.oy;
         base += (n_tiles + tiles_per_wg - 1) / tiles_per_wg;
-        if (base > 0x7fffffffLL / kFieldThreads) return EMDQ_EINVAL;
-        m->last = stream;
+        if (base > 0x7fffffffLL / kFieldThreads) {
+            free(order);
+            return EMDQ_EINVAL;
+        }
     }
-    if (base == 0) return EMDQ_OK;
+    free(order);
+    *blocks_out = base;
+    return EMDQ_OK;
+}
+
+void launch_field_b(int mode, int variant, unsigned blocks, const FieldJob *jobs, int n_jobs,
+                    hipStream_t stream) {
+#define EMDQ_FB(M, K)                                                                       \
+    hipLaunchKernelGGL((k_field_b<M, K>), dim3(blocks), dim3(kFieldThreads), 0, stream, jobs, \
+                       n_jobs)
+    if (mode == kModeField) {
+        if (variant == 1) EMDQ_FB(kModeField, 2);
+        else if (variant == 2) EMDQ_FB(kModeField, 1);
+        else EMDQ_FB(kModeField, 4);
+    } else {
+        if (variant == 1) EMDQ_FB(kModeWarp, 2);
+        else if (variant == 2) EMDQ_FB(kModeWarp, 1);
+        else EMDQ_FB(kModeWarp, 4);
+    }
+#undef EMDQ_FB
+}
+
+emdq_status batch_regions_ok(emdq_batch b, int n_pairs, const emdq_model *models,
+                             const emdq_region *regions, int mode) {
+    if (!b || !models || !regions || n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (!models[i]) return EMDQ_EINVAL;
+        const emdq_status rc = batch_region_ok(regions[i], mode);
+        if (rc != EMDQ_OK) return rc;
+    }
+    return EMDQ_OK;
+}
+
+emdq_status batch_field_launch(emdq_batch b, int n_pairs, const emdq_model *models,
+                               const emdq_region *regions, int mode, hipStream_t stream) {
+    emdq_status rc = batch_regions_ok(b, n_pairs, models, regions, mode);
+    if (rc != EMDQ_OK) return rc;
+    int slot = 0;
+    FieldJob *jobs = (FieldJob *)batch_slot(b, &slot);
+    if (!jobs) return EMDQ_EHIP;
+    long long blocks = 0;
+    rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[b->variant], &blocks);
+    if (rc != EMDQ_OK) return rc;
+    for (int i = 0; i < n_pairs; ++i) models[i]->last = stream;
+    if (blocks == 0) return EMDQ_OK;
     EMDQ_HIP(hipMemcpyAsync(b->field_jobs, jobs, sizeof(FieldJob) * n_pairs,
                             hipMemcpyHostToDevice, stream));
     EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
-    if (mode == kModeField)
-        hipLaunchKernelGGL(k_field_b<kModeField>, dim3((unsigned)base), dim3(kFieldThreads), 0,
-                           stream, b->field_jobs, n_pairs);
-    else
-        hipLaunchKernelGGL(k_field_b<kModeWarp>, dim3((unsigned)base), dim3(kFieldThreads), 0,
-                           stream, b->field_jobs, n_pairs);
+    launch_field_b(mode, b->variant, (unsigned)blocks, b->field_jobs, n_pairs, stream);
     return check_launch();
+}
+
+// Cache of autotuner choices: one "emdq-autotune <tiles bucket> <matches
+// bucket> <variant>" line per entry, buckets being rounded log2 of the total
+// tile count and of the mean match count of the batch.
+int cache_lookup(const char *path, int tb, int nb) {
+    FILE *f = fopen(path, "r");
+    if (!f) return -1;
+    char tag[32];
+    int a, c, v, found = -1;
+    while (fscanf(f, "%31s %d %d %d", tag, &a, &c, &v) == 4)
+        if (strcmp(tag, "emdq-autotune") == 0 && a == tb && c == nb && v >= 0 &&
+            v < kBatchVariants)
+            found = v;
+    fclose(f);
+    return found;
 }
 
 }  // namespace
@@ -2040,9 +2519,13 @@ emdq_status emdq_batch_create(int max_pairs, emdq_batch *out) {
     const size_t n = (size_t)max_pairs;
     bool ok = hipMalloc((void **)&b->em_jobs, n * sizeof(EmJob)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b->field_jobs, n * sizeof(FieldJob)) == hipSuccess;
-    ok = ok && hipMalloc((void **)&b->states, n * sizeof(DevState)) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&b->host_states, n * sizeof(DevState),
+    ok = ok && hipMalloc((void **)&b->start_jobs, n * sizeof(StartJob)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->prepared, n * sizeof(FieldJob)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->states, 2 * n * sizeof(DevState)) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->host_states, 2 * n * sizeof(DevState),
                              hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; ok && k < 2; ++k)
+        ok = hipEventCreateWithFlags(&b->em_ev[k], hipEventDisableTiming) == hipSuccess;
     for (int k = 0; ok && k < emdq_batch_s::kSlots; ++k) {
         ok = hipHostMalloc(&b->stage[k], batch_stage_bytes(max_pairs), hipHostMallocDefault) ==
              hipSuccess;
@@ -2068,15 +2551,20 @@ void emdq_batch_free(emdq_batch b) {
     }
     (void)hipFree(b->em_jobs);
     (void)hipFree(b->field_jobs);
+    (void)hipFree(b->start_jobs);
+    (void)hipFree(b->prepared);
     (void)hipFree(b->states);
     if (b->host_states) (void)hipHostFree(b->host_states);
+    for (int k = 0; k < 2; ++k)
+        if (b->em_ev[k]) (void)hipEventDestroy(b->em_ev[k]);
     delete b;
 }
 
 emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
                            const float *const *src_xy, const float *const *dst_xy,
                            const int *n, const int *frame_w, const int *frame_h,
-                           const emdq_params *params, hipStream_t stream) {
+                           const float *const *init_p, const emdq_params *params,
+                           hipStream_t stream) {
     if (!b || !models || !src_xy || !dst_xy || !n || !frame_w || !frame_h) return EMDQ_EINVAL;
     if (n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
     if (!distinct_models(n_pairs, models)) return EMDQ_EINVAL;
@@ -2085,6 +2573,7 @@ emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
     if (!params_ok(prm)) return EMDQ_EINVAL;
     for (int i = 0; i < n_pairs; ++i) {
         if (!src_xy[i] || !dst_xy[i] || frame_w[i] <= 0 || frame_h[i] <= 0) return EMDQ_EINVAL;
+        if (init_p && !init_p[i]) return EMDQ_EINVAL;
         if (n[i] < 2) return EMDQ_ETOOFEW;
         if (n[i] > models[i]->n_max) return EMDQ_EINVAL;
     }
@@ -2101,6 +2590,7 @@ emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
         EmJob &J = jobs[i];
         J.src = (const float2 *)src_xy[i];
         J.dst = (const float2 *)dst_xy[i];
+        J.init_p = init_p ? init_p[i] : nullptr;
         J.xy = m->xy;
         J.p = m->p;
         J.mask = m->mask;
@@ -2125,14 +2615,16 @@ emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
     const unsigned P = (unsigned)n_pairs;
     hipLaunchKernelGGL(k_reset_b, dim3(P), dim3(64), 0, stream, b->em_jobs);
     hipLaunchKernelGGL(k_load_b, dim3((unsigned)((max_n + 255) / 256), P), dim3(256), 0, stream,
-                       b->em_jobs);
+                       b->em_jobs, prm.p_thresh);
     if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
+    auto mstep_b = [&](int final_pass) {
+        hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0, stream,
+                           b->em_jobs, final_pass);
+    };
     int enqueued = 0;
-    const int chunk = 4;
-    while (true) {
-        for (int c = 0; c < chunk && enqueued < prm.max_iter; ++c, ++enqueued) {
-            hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0,
-                               stream, b->em_jobs, 0);
+    for (int k = 0;; ++k) {
+        for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
+            mstep_b(0);
             hipLaunchKernelGGL(k_estep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0,
                                stream, b->em_jobs);
             hipLaunchKernelGGL(k_posterior_b, dim3(P), dim3(kPostThreads), 0, stream,
@@ -2140,19 +2632,155 @@ emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
                                (double)prm.gamma_max, prm.p_thresh, prm.max_iter);
         }
         hipLaunchKernelGGL(k_gather_states, dim3((P + 63) / 64), dim3(64), 0, stream,
-                           b->em_jobs, n_pairs, b->states);
+                           b->em_jobs, n_pairs, b->states + (size_t)(k & 1) * b->max_pairs);
         if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
-        EMDQ_HIP(hipMemcpyAsync(b->host_states, b->states, sizeof(DevState) * n_pairs,
-                                hipMemcpyDeviceToHost, stream));
-        EMDQ_HIP(hipStreamSynchronize(stream));
-        bool all = true;
-        for (int i = 0; i < n_pairs; ++i)
-            all = all && (b->host_states[i].done || b->host_states[i].status < 0);
-        if (all || enqueued >= prm.max_iter) break;
+        EMDQ_HIP(hipMemcpyAsync(b->host_states + (size_t)(k & 1) * b->max_pairs,
+                                b->states + (size_t)(k & 1) * b->max_pairs,
+                                sizeof(DevState) * n_pairs, hipMemcpyDeviceToHost, stream));
+        EMDQ_HIP(hipEventRecord(b->em_ev[k & 1], stream));
+        if (k > 0) {
+            EMDQ_HIP(hipEventSynchronize(b->em_ev[(k - 1) & 1]));
+            const DevState *prev = b->host_states + (size_t)((k - 1) & 1) * b->max_pairs;
+            bool all = true;
+            for (int i = 0; i < n_pairs; ++i) all = all && (prev[i].done || prev[i].status < 0);
+            if (all) break;
+        }
+        if (enqueued >= prm.max_iter) break;
     }
-    hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0, stream,
-                       b->em_jobs, 1);
+    mstep_b(1);
     hipLaunchKernelGGL(k_compact_b, dim3(P), dim3(kCompactThreads), 0, stream, b->em_jobs);
+    return check_launch();
+}
+
+emdq_status emdq_batch_learned_start(emdq_batch b, int n_pairs, const float *const *src_xy,
+                                     const float *const *dst_xy, const int *n,
+                                     const int *frame_w, const int *frame_h,
+                                     const emdq_params *params, const float *weights,
+                                     float *const *p_out, hipStream_t stream) {
+    if (!b || !src_xy || !dst_xy || !n || !frame_w || !frame_h || !weights || !p_out)
+        return EMDQ_EINVAL;
+    if (n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
+    emdq_params prm;
+    if (params) prm = *params; else emdq_params_default(&prm);
+    if (!params_ok(prm)) return EMDQ_EINVAL;
+    int slot = 0;
+    StartJob *jobs = (StartJob *)batch_slot(b, &slot);
+    if (!jobs) return EMDQ_EHIP;
+    int max_n = 2;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (!src_xy[i] || !dst_xy[i] || !p_out[i] || frame_w[i] <= 0 || frame_h[i] <= 0)
+            return EMDQ_EINVAL;
+        if (n[i] < 2) return EMDQ_ETOOFEW;
+        jobs[i].src = (const float2 *)src_xy[i];
+        jobs[i].dst = (const float2 *)dst_xy[i];
+        jobs[i].p_out = p_out[i];
+        jobs[i].n = n[i];
+        jobs[i].g = (float)sqrt(alpha_d(prm, frame_w[i], frame_h[i]));
+        if (n[i] > max_n) max_n = n[i];
+    }
+    EMDQ_HIP(hipMemcpyAsync(b->start_jobs, jobs, sizeof(StartJob) * n_pairs,
+                            hipMemcpyHostToDevice, stream));
+    EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
+    // enough workgroups per pair to cover the largest one; about 2048 in all
+    int per = (2048 + n_pairs - 1) / n_pairs;
+    const int need = (max_n + kStartWaves - 1) / kStartWaves;
+    if (per > need) per = need;
+    hipLaunchKernelGGL(k_start_b, dim3((unsigned)per, (unsigned)n_pairs), dim3(kStartThreads), 0,
+                       stream, b->start_jobs, weights);
+    return check_launch();
+}
+
+emdq_status emdq_batch_autotune(emdq_batch b, int n_pairs, const emdq_model *models,
+                                const emdq_region *regions, const char *cache_path,
+                                int *variant_out, hipStream_t stream) {
+    emdq_status rc = batch_regions_ok(b, n_pairs, models, regions, kModeField);
+    if (rc != EMDQ_OK) return rc;
+    long long tiles = 0;
+    double nsum = 0.0;
+    for (int i = 0; i < n_pairs; ++i) {
+        tiles += (long long)((regions[i].w + kTile - 1) / kTile) * ((regions[i].h + kTile - 1) / kTile);
+        nsum += models[i]->n;
+    }
+    const int tb = tiles > 0 ? (int)lround(log2((double)tiles)) : 0;
+    const int nb = nsum > 0.0 ? (int)lround(log2(nsum / n_pairs)) : 0;
+    int best = cache_path ? cache_lookup(cache_path, tb, nb) : -1;
+    if (best < 0) {
+        hipEvent_t e0, e1;
+        EMDQ_HIP(hipEventCreate(&e0));
+        EMDQ_HIP(hipEventCreate(&e1));
+        float best_ms = 0.f;
+        for (int v = 0; v < kBatchVariants && rc == EMDQ_OK; ++v) {
+            b->variant = v;
+            for (int rep = 0; rep < 2 && rc == EMDQ_OK; ++rep) {   // warm-up, then timed
+                if (hipEventRecord(e0, stream) != hipSuccess) rc = EMDQ_EHIP;
+                if (rc == EMDQ_OK)
+                    rc = batch_field_launch(b, n_pairs, models, regions, kModeField, stream);
+                if (rc == EMDQ_OK && hipEventRecord(e1, stream) != hipSuccess) rc = EMDQ_EHIP;
+            }
+            float ms = 0.f;
+            if (rc == EMDQ_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = EMDQ_EHIP;
+            if (rc == EMDQ_OK && (best < 0 || ms < best_ms)) {
+                best = v;
+                best_ms = ms;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != EMDQ_OK) {
+            b->variant = 0;
+            return rc;
+        }
+        if (cache_path) {
+            FILE *f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "emdq-autotune %d %d %d\n", tb, nb, best);
+                fclose(f);
+            }
+        }
+    }
+    b->variant = best;
+    if (variant_out) *variant_out = best;
+    return EMDQ_OK;
+}
+
+emdq_status emdq_batch_set_variant(emdq_batch b, int variant) {
+    if (!b || variant < 0 || variant >= kBatchVariants) return EMDQ_EINVAL;
+    b->variant = variant;
+    return EMDQ_OK;
+}
+
+emdq_status emdq_batch_prepare(emdq_batch b, int warp, int n_pairs, const emdq_model *models,
+                               const emdq_region *regions) {
+    const int mode = warp ? kModeWarp : kModeField;
+    emdq_status rc = batch_regions_ok(b, n_pairs, models, regions, mode);
+    if (rc != EMDQ_OK) return rc;
+    FieldJob *jobs = (FieldJob *)malloc(sizeof(FieldJob) * (size_t)n_pairs);
+    if (!jobs) return EMDQ_ENOMEM;
+    long long blocks = 0;
+    rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[b->variant], &blocks);
+    if (rc == EMDQ_OK &&
+        hipMemcpy(b->prepared, jobs, sizeof(FieldJob) * n_pairs, hipMemcpyHostToDevice) !=
+            hipSuccess)
+        rc = EMDQ_EHIP;
+    free(jobs);
+    if (rc != EMDQ_OK) {
+        b->prep_mode = -1;
+        return rc;
+    }
+    b->prep_mode = mode;
+    b->prep_pairs = n_pairs;
+    b->prep_variant = b->variant;
+    b->prep_blocks = blocks;
+    return EMDQ_OK;
+}
+
+emdq_status emdq_batch_launch(emdq_batch b, hipStream_t stream) {
+    if (!b || b->prep_mode < 0) return EMDQ_EINVAL;
+    if (b->prep_blocks == 0) return EMDQ_OK;
+    launch_field_b(b->prep_mode, b->prep_variant, (unsigned)b->prep_blocks, b->prepared,
+                   b->prep_pairs, stream);
     return check_launch();
 }
 

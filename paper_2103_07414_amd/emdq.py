@@ -22,7 +22,10 @@ EXPORTS = ("emdq_params_default", "emdq_alpha", "emdq_model_create", "emdq_model
            "emdq_uncertainty", "emdq_track_nodes", "emdq_model_set_precision",
            "emdq_model_status", "emdq_model_results", "emdq_status_string",
            "emdq_batch_create", "emdq_batch_free", "emdq_batch_fit", "emdq_batch_field",
-           "emdq_batch_warp", "emdq_fit_from", "emdq_learned_start")
+           "emdq_batch_warp", "emdq_fit_from", "emdq_learned_start",
+           "emdq_batch_learned_start", "emdq_start_features", "emdq_start_train_work_floats",
+           "emdq_start_train_step", "emdq_batch_autotune", "emdq_batch_set_variant",
+           "emdq_batch_prepare", "emdq_batch_launch")
 
 START_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "start_mlp.npy")
 N_START_WEIGHTS = 24961
@@ -79,6 +82,12 @@ def lib():
         L.emdq_fit_from.restype = I
         L.emdq_learned_start.argtypes = [P, P, I, I, I, C.POINTER(Params), P, P, P]
         L.emdq_learned_start.restype = I
+        L.emdq_start_features.argtypes = [P, P, I, I, I, C.POINTER(Params), P, P]
+        L.emdq_start_features.restype = I
+        L.emdq_start_train_work_floats.argtypes = [I]
+        L.emdq_start_train_work_floats.restype = C.c_size_t
+        L.emdq_start_train_step.argtypes = [P, P, P, I, P, P, I, P, I, F, I, P, P]
+        L.emdq_start_train_step.restype = I
         L.emdq_model_set_nodes.argtypes = [P, P, P, P, P, I, F, P]
         L.emdq_model_set_nodes.restype = I
         L.emdq_field.argtypes = [P, I, I, I, I, P, P]
@@ -102,12 +111,24 @@ def lib():
         L.emdq_batch_free.restype = None
         PP = C.POINTER(C.c_void_p)
         IP = C.POINTER(C.c_int)
-        L.emdq_batch_fit.argtypes = [P, I, PP, PP, PP, IP, IP, IP, C.POINTER(Params), P]
+        L.emdq_batch_fit.argtypes = [P, I, PP, PP, PP, IP, IP, IP, PP, C.POINTER(Params), P]
+        L.emdq_batch_learned_start.argtypes = [P, I, PP, PP, IP, IP, IP, C.POINTER(Params), P,
+                                               PP, P]
+        L.emdq_batch_learned_start.restype = I
         L.emdq_batch_fit.restype = I
         L.emdq_batch_field.argtypes = [P, I, PP, C.POINTER(Region), P]
         L.emdq_batch_field.restype = I
         L.emdq_batch_warp.argtypes = [P, I, PP, C.POINTER(Region), P]
         L.emdq_batch_warp.restype = I
+        L.emdq_batch_autotune.argtypes = [P, I, PP, C.POINTER(Region), C.c_char_p,
+                                          C.POINTER(I), P]
+        L.emdq_batch_autotune.restype = I
+        L.emdq_batch_set_variant.argtypes = [P, I]
+        L.emdq_batch_set_variant.restype = I
+        L.emdq_batch_prepare.argtypes = [P, I, I, PP, C.POINTER(Region)]
+        L.emdq_batch_prepare.restype = I
+        L.emdq_batch_launch.argtypes = [P, P]
+        L.emdq_batch_launch.restype = I
         L.emdq_status_string.argtypes = [I]
         L.emdq_status_string.restype = C.c_char_p
         _lib = L
@@ -217,6 +238,47 @@ def emdq_learned_start(src, dst, frame_w: int, frame_h: int, weights, out,
         int(frame_w), int(frame_h), C.byref(params) if params is not None else None,
         _dev(weights, torch.float32, "weights"), _dev(out, torch.float32, "out"),
         _stream(stream)), "emdq_learned_start")
+
+
+def emdq_start_features(src, dst, frame_w: int, frame_h: int, out, params: Params | None = None,
+                        stream=None) -> int:
+    """The learned start's features: src, dst CUDA float32 [N, 2]; out
+    CUDA float32 [N, 64]."""
+    import torch
+    if src.shape != dst.shape or src.dim() != 2 or src.shape[1] != 2:
+        raise ValueError("src and dst must both be [N, 2]")
+    if tuple(out.shape) != (src.shape[0], 64):
+        raise ValueError("out must be [N, 64]")
+    return _check(lib().emdq_start_features(
+        _dev(src, torch.float32, "src"), _dev(dst, torch.float32, "dst"), int(src.shape[0]),
+        int(frame_w), int(frame_h), C.byref(params) if params is not None else None,
+        _dev(out, torch.float32, "out"), _stream(stream)), "emdq_start_features")
+
+
+def emdq_start_train_work_floats(groups: int) -> int:
+    return int(lib().emdq_start_train_work_floats(int(groups)))
+
+
+def emdq_start_train_step(weights, adam_m, adam_v, step: int, feat, label, idx, lr: float,
+                          groups: int, work, stream=None) -> int:
+    """One Adam step on the learned start (all CUDA tensors): weights, adam_m,
+    adam_v float32 [24961]; feat float32 [M, 64]; label float32 [M]; idx int32
+    [B]; work float32 [emdq_start_train_work_floats(groups)]."""
+    import torch
+    for t, name in ((weights, "weights"), (adam_m, "adam_m"), (adam_v, "adam_v")):
+        if tuple(t.shape) != (N_START_WEIGHTS,):
+            raise ValueError(f"{name} must be [24961]")
+    m = int(feat.shape[0])
+    if tuple(feat.shape) != (m, 64) or tuple(label.shape) != (m,):
+        raise ValueError("feat must be [M, 64] and label [M]")
+    if work.numel() < emdq_start_train_work_floats(min(groups, int(idx.shape[0]))):
+        raise ValueError("work is too small")
+    return _check(lib().emdq_start_train_step(
+        _dev(weights, torch.float32, "weights"), _dev(adam_m, torch.float32, "adam_m"),
+        _dev(adam_v, torch.float32, "adam_v"), int(step), _dev(feat, torch.float32, "feat"),
+        _dev(label, torch.float32, "label"), m, _dev(idx, torch.int32, "idx"),
+        int(idx.shape[0]), float(lr), int(groups), _dev(work, torch.float32, "work"),
+        _stream(stream)), "emdq_start_train_step")
 
 
 def emdq_model_set_nodes(model: int, x_xy, scale, q, mask, alpha: float, stream=None) -> int:
@@ -382,13 +444,44 @@ class Batch:
     def _handles(models):
         return (C.c_void_p * len(models))(*[m.handle for m in models])
 
-    def fit(self, models, srcs, dsts, sizes, params=None, stream=None):
+    def learned_start(self, srcs, dsts, sizes, weights, outs, params=None, stream=None):
+        """Learned starting posteriors of every pair in one launch: outs are
+        CUDA float32 [N_i]; weights as load_start_weights()."""
+        import torch
+        k = len(srcs)
+        if not (len(dsts) == len(sizes) == len(outs) == k):
+            raise ValueError("srcs, dsts, sizes and outs must have the same length")
+        if tuple(weights.shape) != (N_START_WEIGHTS,):
+            raise ValueError("weights must be [24961]")
+        arr = lambda v, t: (t * k)(*v)
+        ps = [_dev(a, torch.float32, "src") for a in srcs]
+        pd = [_dev(a, torch.float32, "dst") for a in dsts]
+        po = []
+        for a, o in zip(srcs, outs):
+            if tuple(o.shape) != (a.shape[0],):
+                raise ValueError("out must be [N]")
+            po.append(_dev(o, torch.float32, "out"))
+        return _check(lib().emdq_batch_learned_start(
+            self.handle, k, arr(ps, C.c_void_p), arr(pd, C.c_void_p),
+            arr([int(a.shape[0]) for a in srcs], C.c_int), arr([w for w, _ in sizes], C.c_int),
+            arr([h for _, h in sizes], C.c_int),
+            C.byref(params) if params is not None else None,
+            _dev(weights, torch.float32, "weights"), arr(po, C.c_void_p), _stream(stream)),
+            "emdq_batch_learned_start")
+
+    def fit(self, models, srcs, dsts, sizes, params=None, stream=None, init_ps=None):
         """models: list of Model; srcs, dsts: CUDA float32 [N_i, 2];
-        sizes: list of (frame_w, frame_h)."""
+        sizes: list of (frame_w, frame_h); init_ps: None (plain start) or
+        CUDA float32 [N_i] starting posteriors per pair."""
         import torch
         k = len(models)
         if not (len(srcs) == len(dsts) == len(sizes) == k):
             raise ValueError("models, srcs, dsts and sizes must have the same length")
+        pi = None
+        if init_ps is not None:
+            if len(init_ps) != k:
+                raise ValueError("init_ps must have one entry per pair")
+            pi = (C.c_void_p * k)(*[_dev(t, torch.float32, "init_p") for t in init_ps])
         ps, pd, ns = [], [], []
         for m, a, b in zip(models, srcs, dsts):
             if a.shape != b.shape or a.dim() != 2 or a.shape[1] != 2:
@@ -401,7 +494,7 @@ class Batch:
         return _check(lib().emdq_batch_fit(
             self.handle, k, self._handles(models), arr(ps, C.c_void_p), arr(pd, C.c_void_p),
             arr(ns, C.c_int), arr([w for w, _ in sizes], C.c_int),
-            arr([h for _, h in sizes], C.c_int),
+            arr([h for _, h in sizes], C.c_int), pi,
             C.byref(params) if params is not None else None, _stream(stream)),
             "emdq_batch_fit")
 
@@ -416,6 +509,70 @@ class Batch:
             r.out_xy = _dev(o, torch.float32, "out")
         return _check(lib().emdq_batch_field(self.handle, len(models), self._handles(models),
                                              regs, _stream(stream)), "emdq_batch_field")
+
+    @staticmethod
+    def _field_regions(models, rects, outs):
+        import torch
+        regs = (Region * len(models))()
+        for r, (zx0, zy0, w, h), o in zip(regs, rects, outs):
+            if tuple(o.shape) != (h, w, 2):
+                raise ValueError("out must be [h, w, 2]")
+            r.zx0, r.zy0, r.w, r.h = zx0, zy0, w, h
+            r.out_xy = _dev(o, torch.float32, "out")
+        return regs
+
+    @staticmethod
+    def _warp_regions(models, frames, canvases, offsets, rects):
+        import torch
+        regs = (Region * len(models))()
+        for r, f, c, (ox, oy), (zx0, zy0, w, h) in zip(regs, frames, canvases, offsets, rects):
+            if f.dim() != 3 or f.shape[2] != 3 or c.dim() != 3 or c.shape[2] != 4:
+                raise ValueError("frame must be [fh, fw, 3] and canvas [ch, cw, 4]")
+            r.zx0, r.zy0, r.w, r.h = zx0, zy0, w, h
+            r.frame_rgb = _dev(f, torch.uint8, "frame")
+            r.fh, r.fw = int(f.shape[0]), int(f.shape[1])
+            r.frame_pitch_bytes = 3 * r.fw
+            r.canvas = _dev(c, torch.float32, "canvas")
+            r.ch, r.cw = int(c.shape[0]), int(c.shape[1])
+            r.canvas_pitch_px = r.cw
+            r.ox, r.oy = ox, oy
+        return regs
+
+    def autotune(self, models, rects, outs, cache_path=None, stream=None) -> int:
+        """Times the field-kernel shapes on batch_field(models, rects, outs)
+        and keeps the fastest; returns its index."""
+        regs = self._field_regions(models, rects, outs)
+        v = C.c_int(-1)
+        _check(lib().emdq_batch_autotune(self.handle, len(models), self._handles(models), regs,
+                                         None if cache_path is None else
+                                         os.fsencode(cache_path), C.byref(v),
+                                         _stream(stream)), "emdq_batch_autotune")
+        return v.value
+
+    def set_variant(self, variant: int):
+        return _check(lib().emdq_batch_set_variant(self.handle, int(variant)),
+                      "emdq_batch_set_variant")
+
+    def prepare_field(self, models, rects, outs):
+        """Job table of a batched field launch for launch() (host-blocking)."""
+        self._keep = (models, outs)
+        return _check(lib().emdq_batch_prepare(self.handle, 0, len(models),
+                                               self._handles(models),
+                                               self._field_regions(models, rects, outs)),
+                      "emdq_batch_prepare")
+
+    def prepare_warp(self, models, frames, canvases, offsets, rects):
+        self._keep = (models, frames, canvases)
+        return _check(lib().emdq_batch_prepare(self.handle, 1, len(models),
+                                               self._handles(models),
+                                               self._warp_regions(models, frames, canvases,
+                                                                  offsets, rects)),
+                      "emdq_batch_prepare")
+
+    def launch(self, stream=None):
+        """The prepared launch: one kernel, capturable in a graph."""
+        return _check(lib().emdq_batch_launch(self.handle, _stream(stream)),
+                      "emdq_batch_launch")
 
     def warp(self, models, frames, canvases, offsets, rects, stream=None):
         """frames: CUDA uint8 [fh, fw, 3]; canvases: CUDA float32 [ch, cw, 4];

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_function():
     from paper_2103_07414_amd import emdq as E
     L = E.lib()
     names = header_functions()
-    assert len(names) == 21
+    assert len(names) == 29
     assert sorted(E.EXPORTS) == names
     for name in names:
         assert hasattr(L, name), name
@@ -49,9 +49,21 @@ def test_host_only_calls():
     assert L.emdq_uncertainty(None, 1e-3, 0, 0, 4, 4, None, None) == E.EINVAL
     assert L.emdq_track_nodes(None, 1e-3, 4, None, None, None, None, None) == E.EINVAL
     assert L.emdq_batch_create(0, C.byref(h)) == E.EINVAL
-    assert L.emdq_batch_fit(None, 1, None, None, None, None, None, None, None, None) == E.EINVAL
+    assert L.emdq_batch_fit(None, 1, None, None, None, None, None, None, None, None,
+                            None) == E.EINVAL
+    assert L.emdq_batch_learned_start(None, 1, None, None, None, None, None, None, None, None,
+                                      None) == E.EINVAL
     assert L.emdq_batch_warp(None, 1, None, None, None) == E.EINVAL
     L.emdq_batch_free(None)
+    assert L.emdq_batch_autotune(None, 1, None, None, None, None, None) == E.EINVAL
+    assert L.emdq_batch_set_variant(None, 0) == E.EINVAL
+    assert L.emdq_batch_prepare(None, 0, 1, None, None) == E.EINVAL
+    assert L.emdq_batch_launch(None, None) == E.EINVAL
+    assert L.emdq_start_features(None, None, 4, 10, 10, None, None, None) == E.EINVAL
+    assert L.emdq_start_train_work_floats(0) == 0
+    assert L.emdq_start_train_work_floats(3) == 4 * 24962
+    assert L.emdq_start_train_step(None, None, None, 1, None, None, 4, None, 4, 1e-3, 1, None,
+                                   None) == E.EINVAL
     assert L.emdq_fit_from(None, None, None, 4, 10, 10, None, None, None) == E.EINVAL
     assert L.emdq_learned_start(None, None, 4, 10, 10, None, None, None, None) == E.EINVAL
     L.emdq_model_free(None)

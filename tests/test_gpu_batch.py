@@ -1,7 +1,8 @@
 """Batched pairs: one launch per EM phase for all pairs, one flat launch for
-all fields / warps.  The batch must give exactly the bits of the single-pair
-calls (same kernels, same per-pair arithmetic), and through them the
-oracle's masks, iteration counts and field tolerance."""
+all fields / warps.  With the default field-kernel shape the batch must give
+exactly the bits of the single-pair calls (same kernels, same per-pair
+arithmetic), and through them the oracle's masks, iteration counts and field
+tolerance."""
 import numpy as np
 import pytest
 
@@ -109,3 +110,88 @@ def test_batch_argument_errors():
     b3 = E.Batch(1)
     with pytest.raises(E.EmdqError):          # more pairs than the batch holds
         b3.fit([m, E.Model(3000)], src, dst, sizes)
+
+
+def test_batch_learned_start_and_fit_from_match_single_calls():
+    """Batched learned start = per-pair emdq_learned_start, and the batch EM
+    from those starts = per-pair emdq_fit_from, bit for bit."""
+    torch = torch_or_skip()
+    E = emdq()
+    pairs = synth.gen_batch(5, seed=3019, with_frame=False)
+    w = E.load_start_weights()
+    srcs = [to_dev(p.src, torch) for p in pairs]
+    dsts = [to_dev(p.dst, torch) for p in pairs]
+    sizes = [(p.cfg.width, p.cfg.height) for p in pairs]
+    outs_b = [torch.empty(p.cfg.n_matches, dtype=torch.float32, device="cuda") for p in pairs]
+    b = E.Batch(5)
+    b.learned_start(srcs, dsts, sizes, w, outs_b)
+    mb = [E.Model(p.cfg.n_matches) for p in pairs]
+    b.fit(mb, srcs, dsts, sizes, init_ps=outs_b)
+    for i, p in enumerate(pairs):
+        o = torch.empty(p.cfg.n_matches, dtype=torch.float32, device="cuda")
+        E.emdq_learned_start(srcs[i], dsts[i], *sizes[i], w, o)
+        assert torch.equal(o, outs_b[i]), i
+        m = E.Model(p.cfg.n_matches)
+        m.fit_from(srcs[i], dsts[i], *sizes[i], o)
+        rs, rb = m.results(), mb[i].results()
+        assert rs["iters"] == rb["iters"], i
+        for key in ("p", "q", "scale", "mask"):
+            assert np.array_equal(rs[key], rb[key]), (i, key)
+
+
+def test_batch_autotune_variants_and_cache(tmp_path):
+    """Every field-kernel shape the autotuner picks from meets the oracle
+    bar and repeats its own bits; the choice is cached and read back."""
+    torch = torch_or_skip()
+    pairs = synth.gen_batch(4, seed=3023, with_frame=False)
+    E, b, mb, _ = _batch_and_singles(torch, pairs)
+    rects = [(0, 0, p.cfg.width, p.cfg.height) for p in pairs]
+    outs = [torch.empty((p.cfg.height, p.cfg.width, 2), dtype=torch.float32, device="cuda")
+            for p in pairs]
+    cache = str(tmp_path / "tune.txt")
+    v = b.autotune(mb, rects, outs, cache_path=cache)
+    assert v in (0, 1, 2)
+    assert b.autotune(mb, rects, outs, cache_path=cache) == v
+    assert len(open(cache).read().splitlines()) == 1
+    refs = [O.fit(p.src, p.dst, p.cfg.width, p.cfg.height) for p in pairs]
+    for var in (0, 1, 2):
+        b.set_variant(var)
+        b.field(mb, rects, outs)
+        first = [o.clone() for o in outs]
+        b.field(mb, rects, outs)
+        for i, (p, ref) in enumerate(zip(pairs, refs)):
+            assert torch.equal(first[i], outs[i]), (var, i)
+            rng = np.random.default_rng(i)
+            pts = rng.integers(0, [p.cfg.width, p.cfg.height], (800, 2)).astype(np.float64)
+            _, want = O.field_points(p.src, ref.scale, ref.q, ref.mask, ref.alpha, pts)
+            g = outs[i].cpu().numpy()[pts[:, 1].astype(int), pts[:, 0].astype(int)]
+            assert np.abs(g - want).max() <= FIELD_TOL_PX, (var, i)
+
+
+def test_batch_prepared_launch_in_a_graph():
+    """The prepared batched field launch captured in a graph: every replay,
+    with eager work in between, equals the eager batched call."""
+    torch = torch_or_skip()
+    pairs = synth.gen_batch(3, seed=3029, with_frame=False)
+    E, b, mb, _ = _batch_and_singles(torch, pairs)
+    rects = [(0, 0, p.cfg.width, p.cfg.height) for p in pairs]
+    eager = [torch.empty((p.cfg.height, p.cfg.width, 2), dtype=torch.float32, device="cuda")
+             for p in pairs]
+    b.field(mb, rects, eager)
+    outs = [torch.zeros_like(e) for e in eager]
+    b.prepare_field(mb, rects, outs)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            b.launch()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in outs:
+            o.zero_()                      # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(pairs)):
+            assert torch.equal(outs[i], eager[i]), (rep, i)

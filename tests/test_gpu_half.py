@@ -144,3 +144,29 @@ def test_half_deterministic_and_f32_restored():
     assert np.array_equal(outs["b"], outs["c"])
     assert np.array_equal(outs["a"], outs["d"])
     assert not np.array_equal(outs["a"], outs["b"])
+
+
+def test_half_field_in_slabs_matches_oracle():
+    """A region wider than the factor tables (4096 columns) is processed in
+    slabs; every column, across the slab seam, against the oracle."""
+    torch = torch_or_skip()
+    E = emdq()
+    P = synth.gen_config(1, 2, with_frame=False)
+    ref = oracle_fit(P)
+    m = E.Model(P.cfg.n_matches)
+    m.set_precision("f16")
+    m.set_nodes(P.src, ref.scale.astype(np.float32), ref.q.astype(np.float32), ref.mask,
+                ref.alpha)
+    zx0, zy0, w, h = -3900, 100, 4200, 5
+    out = torch.empty((h, w, 2), dtype=torch.float32, device="cuda")
+    m.field(zx0, zy0, w, h, out)
+    s32 = ref.scale.astype(np.float32).astype(np.float64)
+    q32 = ref.q.astype(np.float32).astype(np.float64)
+    # far left the weights vanish (NaN on both sides); compare where the
+    # oracle is finite and the blend is well conditioned
+    rc, want = O.field(P.src, s32, q32, ref.mask, float(np.float32(ref.alpha)), zx0, zy0, w, h)
+    got = out.cpu().numpy()
+    near = np.arange(w) + zx0 >= -40
+    err = np.abs(got[:, near] - want[:, near]).max()
+    print(f"slab field max err {err:.2e} px over {near.sum()} columns", flush=True)
+    assert err <= HALF_TOL_PX["f16"]

@@ -91,3 +91,82 @@ def test_fit_from_nonfinite_start_reported():
     m = E.Model(200)
     m.fit_from(to_dev(P.src, torch), to_dev(P.dst, torch), 320, 240, init)
     assert m.status() == E.ENONFINITE
+
+
+# ------------------------------------------------- training kernels -------
+# Tolerances: features are FP32 images of FP64 values of size <= ~2 (g d
+# with d up to the 16th neighbour) and < 1 (ss), so 1e-5 absolute.  The
+# minibatch gradient is an FP32 sum over 4096 samples of terms with a spread
+# of signs; against the FP64 oracle it is held to 1e-4 of the largest
+# gradient component.
+
+def test_start_features_match_oracle():
+    torch = torch_or_skip()
+    E = emdq()
+    P = synth.gen_config(2, 2, with_frame=False)
+    out = torch.empty((2000, 64), dtype=torch.float32, device="cuda")
+    E.emdq_start_features(to_dev(P.src, torch), to_dev(P.dst, torch), 1280, 1024, out)
+    want = O.init_features(P.src, P.dst, O.alpha(1280, 1024))
+    err = np.abs(out.cpu().numpy() - want).max()
+    print(f"features max abs err {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_train_step_gradient_and_adam_update():
+    torch = torch_or_skip()
+    E = emdq()
+    rng = np.random.default_rng(12)
+    M, B, G = 6000, 4096, 48
+    feat = rng.normal(0, 0.7, (M, 64)).astype(np.float32)
+    label = (rng.uniform(size=M) > 0.3).astype(np.float32)
+    idx = rng.choice(M, B, replace=False).astype(np.int32)
+    w0 = np.load(E.START_WEIGHTS, allow_pickle=False)
+    w = to_dev(w0.copy(), torch)
+    m1 = torch.zeros_like(w)
+    m2 = torch.zeros_like(w)
+    work = torch.zeros(E.emdq_start_train_work_floats(G), dtype=torch.float32, device="cuda")
+    lr = 1e-3
+    E.emdq_start_train_step(w, m1, m2, 1, to_dev(feat, torch), to_dev(label, torch),
+                            to_dev(idx, torch), lr, G, work)
+    res = work.cpu().numpy()[G * 24962:(G + 1) * 24962].astype(np.float64)
+    g_gpu, loss_gpu = res[:24961], res[24961]
+    loss, g = O.start_grad(feat[idx], label[idx], w0.astype(np.float64))
+    err = np.abs(g_gpu - g).max() / np.abs(g).max()
+    print(f"train step: loss {loss_gpu:.6f} / {loss:.6f}, gradient rel err {err:.2e}", flush=True)
+    assert err <= 1e-4 and abs(loss_gpu - loss) <= 1e-4 * max(1.0, loss)
+    # Adam's first step moves every weight by lr * g / (|g| + eps)
+    dw = (w.cpu().numpy().astype(np.float64) - w0) / lr
+    big = np.abs(g_gpu) > 1e-4
+    assert np.allclose(dw[big], -np.sign(g_gpu[big]), atol=1e-3)
+
+
+def test_training_lowers_the_loss_on_plain_emdq_labels():
+    """A few hundred steps on features of three pairs labelled by the plain
+    GPU EMDQ lower the loss below that of the network at start."""
+    torch = torch_or_skip()
+    E = emdq()
+    feats, labels = [], []
+    for cfg, pair in [(2, 1), (2, 2), (1, 1)]:
+        P = synth.gen_config(cfg, pair, with_frame=False)
+        s, d = to_dev(P.src, torch), to_dev(P.dst, torch)
+        m = E.Model(P.cfg.n_matches)
+        m.fit(s, d, P.cfg.width, P.cfg.height)
+        f = torch.empty((P.cfg.n_matches, 64), dtype=torch.float32, device="cuda")
+        E.emdq_start_features(s, d, P.cfg.width, P.cfg.height, f)
+        feats.append(f)
+        labels.append(torch.from_numpy(m.results()["mask"].astype(np.float32)).cuda())
+    feat, label = torch.cat(feats), torch.cat(labels)
+    M = feat.shape[0]
+    rng = np.random.default_rng(4)
+    w = torch.from_numpy(rng.normal(0, 0.05, 24961).astype(np.float32)).cuda()
+    m1, m2 = torch.zeros_like(w), torch.zeros_like(w)
+    G = 32
+    work = torch.zeros(E.emdq_start_train_work_floats(G), dtype=torch.float32, device="cuda")
+    losses = []
+    for step in range(1, 301):
+        idx = torch.from_numpy(rng.choice(M, 1024, replace=False).astype(np.int32)).cuda()
+        E.emdq_start_train_step(w, m1, m2, step, feat, label, idx, 2e-3, G, work)
+        if step in (1, 300):
+            losses.append(float(work[G * 24962 + 24961].item()))
+    print(f"training loss {losses[0]:.4f} -> {losses[1]:.4f}", flush=True)
+    assert losses[1] < 0.5 * losses[0]

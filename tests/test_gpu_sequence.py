@@ -1,0 +1,82 @@
+"""A multi-frame mosaic over a synthetic sequence: the SLAM-adjacent loop of
+Sec. III run step by step on the GPU and in the FP64 oracle.
+
+Per step t (frame t-1 -> t): EMDQ fit of the step's matches; one tracking
+step of the deformation nodes (their warp functions, uncertainties and
+positions; App. A, Eqs. (8)-(9)); the frame of step t warped into the
+mosaic through the nodes' warp functions (Eqs. (2)-(4), (1), Sec. III-F,
+Eqs. (23)-(24)).  The two sides start from the same nodes and inputs and
+each carries its own state forward.
+
+Tolerances: each step adds at most the single-step errors (node position
+1e-3 px, warp function 2e-3 px, scale 1e-5, uncertainty 3e-5 relative), so
+after T steps T times those; the mosaic's colours stay within 1 level away
+from the frame border (validity may flip within the field tolerance of it)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2103_07414_amd import synth
+
+from gpu_util import border_mask, emdq, gpu_fit, oracle_fit, to_dev, torch_or_skip
+from test_gpu_slam import beta_for
+
+pytestmark = pytest.mark.gpu
+
+
+def test_sequence_mosaic_and_nodes_match_oracle():
+    torch = torch_or_skip()
+    E = emdq()
+    steps = [synth.gen_config(1, k) for k in range(1, 6)]       # 5 frame-to-frame steps
+    W, H = steps[0].cfg.width, steps[0].cfg.height
+    cw, ch, ox, oy = synth.canvas_layout(steps[0].cfg)
+    alpha = float(np.float32(O.alpha(W, H)))
+    beta = beta_for(W, H)
+    gy, gx = np.mgrid[0:H:20, 0:W:20]
+    x0 = np.stack([gx.ravel(), gy.ravel()], 1).astype(np.float32)
+    n = len(x0)
+    ident = np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1))
+    # GPU state
+    g_pos, g_s = to_dev(x0.copy(), torch), to_dev(np.ones(n, np.float32), torch)
+    g_q, g_sig = to_dev(ident.copy(), torch), to_dev(np.zeros(n, np.float32), torch)
+    g_canvas = torch.zeros((ch, cw, 4), dtype=torch.float32, device="cuda")
+    nodes = E.Model(n)
+    # oracle state
+    o_pos, o_s = x0.astype(np.float64), np.ones(n)
+    o_q, o_sig = ident.astype(np.float64), np.zeros(n)
+    o_canvas = np.zeros((ch, cw, 4))
+    near = np.zeros((H, W), bool)
+    for t, P in enumerate(steps, 1):
+        m = E.Model(P.cfg.n_matches)
+        gpu_fit(m, P, torch)
+        m.track_nodes(beta, g_pos, g_s, g_q, g_sig)
+        nodes.set_nodes(x0, g_s.cpu().numpy(), g_q.cpu().numpy(), None, alpha)
+        nodes.warp(to_dev(P.frame, torch), g_canvas, ox, oy, 0, 0, W, H)
+
+        ref = oracle_fit(P)
+        rc, o_pos, o_s, o_q, o_sig = O.track_nodes(P.src, ref.scale, ref.q, ref.mask, ref.alpha,
+                                                   beta, o_pos, o_s, o_q, o_sig)
+        assert rc == 0
+        ones = np.ones(n, np.uint8)
+        rc, o_canvas, _ = O.warp(x0, o_s, o_q, ones, alpha, P.frame, o_canvas, ox, oy, 0, 0,
+                                 W, H)
+        _, u = O.field(x0, o_s, o_q, ones, alpha, 0, 0, W, H)
+        near |= border_mask(u, W, H, eps=t * 2e-3)
+
+        e_pos = np.abs(g_pos.cpu().numpy() - o_pos).max()
+        gs, gq = g_s.cpu().numpy().astype(np.float64), g_q.cpu().numpy().astype(np.float64)
+        e_fn = max(np.abs(np.array(O.warp_point(gs[i], gq[i], *x0[i])) -
+                          np.array(O.warp_point(o_s[i], o_q[i], *x0[i]))).max() for i in range(n))
+        e_sig = np.abs(g_sig.cpu().numpy() / o_sig - 1).max()
+        print(f"step {t}: node pos err {e_pos:.2e} px, warp-fn err {e_fn:.2e} px, "
+              f"sigma2 rel {e_sig:.2e}", flush=True)
+        assert e_pos <= t * 1e-3 and e_fn <= t * 2e-3 and e_sig <= t * 3e-5
+        assert np.abs(gs / o_s - 1).max() <= t * 1e-5
+    got = g_canvas.cpu().numpy()
+    keep = np.ones((ch, cw), bool)
+    keep[oy:oy + H, ox:ox + W] = ~near
+    d = np.abs(got - o_canvas)[keep]
+    print(f"mosaic after {len(steps)} frames: max colour err {d[:, :3].max():.3e}, "
+          f"border-excluded {near.sum()}", flush=True)
+    assert d[:, 3].max() == 0.0 and d[:, :3].max() <= 1.0
+    assert (got[oy:oy + H, ox:ox + W, 3] > 0).mean() > 0.5      # the frames were merged
