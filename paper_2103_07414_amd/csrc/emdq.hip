@@ -55,8 +55,18 @@ constexpr int kBufferFlags = 0x00020000;   // raw buffer resource word 3 (gfx9 f
 #endif
 
 constexpr int kRing = EMDQ_RING;       // field kernel: record ring depth (K steps)
+#ifndef EMDQ_FIELD_WAVES
+#define EMDQ_FIELD_WAVES 3
+#endif
+// FP32 field kernel: wavefronts per SIMD the register allocation is held to
+// (3 keeps at least two wavefronts on every SIMD through the last partial
+// round of tiles; 4 spills)
+constexpr int kFieldWaves = EMDQ_FIELD_WAVES;
 #ifndef EMDQ_HALF_TABLES
 #define EMDQ_HALF_TABLES 1  // half-precision blend: factor tables instead of in-loop exps
+#endif
+#ifndef EMDQ_WARP_BATCH
+#define EMDQ_WARP_BATCH 1   // warp epilogue: a lane's pixels merged with batched loads
 #endif
 #ifndef EMDQ_EM_CHUNK
 #define EMDQ_EM_CHUNK 2
@@ -631,7 +641,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(
 // of the tile's accumulator registers.
 template <int SPLITK, int RB>
 struct FieldLds {
-    float part[SPLITK > 1 ? 4 : 1][SPLITK > 1 ? RB * 6 * (16 - 16 / SPLITK) : 1][kWave];
+    float part[SPLITK > 1 ? 4 : 1][SPLITK > 1 ? RB * 3 * (16 - 16 / SPLITK) : 1][kWave];
 };
 
 enum { kModeField = 0, kModeWarp = 1 };
@@ -640,7 +650,7 @@ enum { kModeField = 0, kModeWarp = 1 };
 // and running-average merge into canvas pixel z + (ox, oy); pixels whose u
 // leaves [0, fw-1] x [0, fh-1] are left unchanged.  With integer z the sample
 // cell and the bilinear weights come from d alone, so u is never rounded.
-__device__ __forceinline__ void warp_merge(int zx, int zy, float2 d,
+[[maybe_unused]] __device__ __forceinline__ void warp_merge(int zx, int zy, float2 d,
                                            const uint8_t *__restrict__ frame, int fw, int fh,
                                            int fpitch, float4 *__restrict__ canvas, int cpitch,
                                            int ox, int oy) {
@@ -669,6 +679,67 @@ __device__ __forceinline__ void warp_merge(int zx, int zy, float2 d,
     cur.z = (A * cur.z + v[2]) / A1;
     cur.w = fminf(A1, 30.f);
     *px = cur;
+}
+
+// warp_merge for NB pixels of one lane, with the same arithmetic for every
+// pixel it merges.  All loads are issued before any is used: the sample cell
+// of a pixel that is not merged is clamped into the frame, and the canvas
+// read of a pixel outside the region goes to the region origin, so every
+// load is in bounds and none waits behind another.  Only merged pixels are
+// stored; the pixels are distinct, so no store feeds a later load.
+template <int NB>
+__device__ __forceinline__ void warp_merge_batch(const int (&zx)[NB], const int (&zy)[NB],
+                                                 const float2 (&d)[NB], const bool (&live)[NB],
+                                                 int zx0, int zy0,
+                                                 const uint8_t *__restrict__ frame, int fw,
+                                                 int fh, int fpitch, float4 *__restrict__ canvas,
+                                                 int cpitch, int ox, int oy) {
+    bool ok[NB];
+    float ax[NB], by[NB];
+    uint8_t p[NB][4][3];   // corners 00, 01, 10, 11; channels
+    float4 cur[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const float fzx = (float)zx[i], fzy = (float)zy[i];
+        ok[i] = live[i] && d[i].x >= -fzx && d[i].x <= (float)(fw - 1 - zx[i]) &&
+                d[i].y >= -fzy && d[i].y <= (float)(fh - 1 - zy[i]);
+        const float dx = ok[i] ? d[i].x : 0.f, dy = ok[i] ? d[i].y : 0.f;
+        const float flx = floorf(dx), fly = floorf(dy);
+        const int x0 = min(max(zx[i] + (int)flx, 0), fw - 1);
+        const int y0 = min(max(zy[i] + (int)fly, 0), fh - 1);
+        const int x1 = min(x0 + 1, fw - 1), y1 = min(y0 + 1, fh - 1);
+        ax[i] = dx - flx;
+        by[i] = dy - fly;
+        const uint8_t *row0 = frame + (size_t)y0 * fpitch;
+        const uint8_t *row1 = frame + (size_t)y1 * fpitch;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            p[i][0][ch] = row0[3 * x0 + ch];
+            p[i][1][ch] = row0[3 * x1 + ch];
+            p[i][2][ch] = row1[3 * x0 + ch];
+            p[i][3][ch] = row1[3 * x1 + ch];
+        }
+        const int cx = live[i] ? zx[i] : zx0, cy = live[i] ? zy[i] : zy0;
+        cur[i] = canvas[(size_t)(cy + oy) * cpitch + (cx + ox)];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if (!ok[i]) continue;
+        const float w00 = (1.f - ax[i]) * (1.f - by[i]), w01 = ax[i] * (1.f - by[i]);
+        const float w10 = (1.f - ax[i]) * by[i], w11 = ax[i] * by[i];
+        float v[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+            v[ch] = w00 * (float)p[i][0][ch] + w01 * (float)p[i][1][ch] +
+                    w10 * (float)p[i][2][ch] + w11 * (float)p[i][3][ch];
+        float4 c = cur[i];
+        const float A = c.w, A1 = A + 1.f;
+        c.x = (A * c.x + v[0]) / A1;
+        c.y = (A * c.y + v[1]) / A1;
+        c.z = (A * c.z + v[2]) / A1;
+        c.w = fminf(A1, 30.f);
+        canvas[(size_t)(zy[i] + oy) * cpitch + (zx[i] + ox)] = c;
+    }
 }
 
 // RB row blocks of 32 share the B operands: a wavefront's tile is 32 RB rows x
@@ -781,7 +852,11 @@ __device__ __forceinline__ void field_body(
     // of every row block
     const int rbase = ks * kRegsOwned;
     if constexpr (SPLITK > 1) {
-        {
+        // two passes of three components each, so the partials need half
+        // the LDS
+#pragma unroll
+        for (int c0 = 0; c0 < 6; c0 += 3) {
+            if (c0 > 0) __syncthreads();   // the first pass's reads are done
             int slot = 0;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -789,13 +864,11 @@ __device__ __forceinline__ void field_body(
 #pragma unroll
                 for (int bl = 0; bl < RB; ++bl)
 #pragma unroll
-                    for (int c = 0; c < 6; ++c)
-                        lds.part[wave][(slot * RB + bl) * 6 + c][lane] = acc[bl][c][r];
+                    for (int c = 0; c < 3; ++c)
+                        lds.part[wave][(slot * RB + bl) * 3 + c][lane] = acc[bl][c0 + c][r];
                 ++slot;
             }
-        }
-        __syncthreads();
-        {
+            __syncthreads();
             // add the partials in wavefront order 0, 1, ..., SPLITK-1
             const int wbase = (wave / SPLITK) * SPLITK;
 #pragma unroll
@@ -804,51 +877,63 @@ __device__ __forceinline__ void field_body(
 #pragma unroll
                 for (int bl = 0; bl < RB; ++bl)
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) {
+                    for (int c = 0; c < 3; ++c) {
                         float sum = 0.f;
                         for (int src = 0; src < SPLITK; ++src) {
                             float v;
                             if (src == ks) {
-                                v = acc[bl][c][r];
+                                v = acc[bl][c0 + c][r];
                             } else {
                                 // slot of register r in wavefront src's list
                                 const int src_base = src * kRegsOwned;
                                 const int sl = r < src_base ? r : r - kRegsOwned;
-                                v = lds.part[wbase + src][(sl * RB + bl) * 6 + c][lane];
+                                v = lds.part[wbase + src][(sl * RB + bl) * 3 + c][lane];
                             }
                             sum = src == 0 ? v : sum + v;
                         }
-                        acc[bl][c][r] = sum;
+                        acc[bl][c0 + c][r] = sum;
                     }
             }
         }
     }
     if (tile >= n_tiles) return;
 
-    // ---- epilogue: DQ normalisation, Eq. (1), then (warp) sample + merge
+    // ---- epilogue: DQ normalisation, Eq. (1), then (warp) sample + merge,
+    // in groups of kGroupPix pixels per lane (fewer where more accumulator
+    // registers are still live, so that nothing spills)
+    constexpr int kGroupPix = SPLITK >= 4 ? 4 : 2;
+    int pzx[kGroupPix], pzy[kGroupPix];
+    float2 pd[kGroupPix];
+    bool live[kGroupPix];
 #pragma unroll
     for (int bl = 0; bl < RB; ++bl)
 #pragma unroll
     for (int rr = 0; rr < kRegsOwned; ++rr) {
-        const int r = rbase + rr;
+        const int r = rbase + rr, i = rr % kGroupPix;
         const int zx = px0 + col;
         const int zy = py0 + kTile * bl + 8 * (r >> 2) + 4 * half + (r & 3);
-        if (zx >= zx0 + w || zy >= zy0 + h) continue;
         const float fzx = (float)zx, fzy = (float)zy;
-        const float2 d = blend_displacement(acc[bl][5][r], acc[bl][0][r], acc[bl][1][r],
-                                            acc[bl][2][r], acc[bl][3][r], acc[bl][4][r], fzx, fzy);
+        pzx[i] = zx;
+        pzy[i] = zy;
+        live[i] = zx < zx0 + w && zy < zy0 + h;
+        pd[i] = blend_displacement(acc[bl][5][r], acc[bl][0][r], acc[bl][1][r], acc[bl][2][r],
+                                   acc[bl][3][r], acc[bl][4][r], fzx, fzy);
         if constexpr (MODE == kModeField) {
-            float2 o = bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
-                           : make_float2(fzx + d.x, fzy + d.y);
-            out[(size_t)(zy - zy0) * w + (zx - zx0)] = o;
-        } else {
-            warp_merge(zx, zy, d, frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
+            if (live[i])
+                out[(size_t)(zy - zy0) * w + (zx - zx0)] =
+                    bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
+                        : make_float2(fzx + pd[i].x, fzy + pd[i].y);
+        } else if constexpr (!EMDQ_WARP_BATCH) {
+            if (live[i]) warp_merge(zx, zy, pd[i], frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
+        } else if (i == kGroupPix - 1) {
+            warp_merge_batch<kGroupPix>(pzx, pzy, pd, live, zx0, zy0, frame, fw, fh, fpitch,
+                                        canvas, cpitch, ox, oy);
         }
     }
 }
 
 template <int MODE, int SPLITK, int RB>
-__global__ __launch_bounds__(kFieldThreads) void k_field(
+__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(kFieldWaves, kFieldWaves))) void k_field(
     const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
     int zy0, int w, int h, int tiles_x, int n_tiles, float2 *__restrict__ out,
     const uint8_t *__restrict__ frame, int fw, int fh, int fpitch, float4 *__restrict__ canvas,
@@ -905,12 +990,35 @@ template <> struct HalfT<kDtBF16> {
     using Q = float;      // BF16 products are formed in FP32, then rounded
 };
 
+// Three chunk buffers: with factor tables, chunk c + 2 is stored while chunk
+// c is multiplied, so chunk c + 1 is complete one barrier early and its
+// first operands can be read before that barrier (the generating path uses
+// two of them).
 template <int DT>
 struct alignas(16) HalfLds {
-    typename HalfT<DT>::T gy[2][kHTy][kHStride];
-    typename HalfT<DT>::T gx[2][kHTx][kHStride];
-    typename HalfT<DT>::Q qd[2][5][kHK];
+    typename HalfT<DT>::T gy[3][kHTy][kHStride];
+    typename HalfT<DT>::T gx[3][kHTx][kHStride];
+    typename HalfT<DT>::Q qd[3][5][kHK];
     float red[4][8];
+};
+
+// Operands of one K step of the half-precision blend, held in registers.
+template <int DT> struct KOps;
+template <> struct KOps<kDtF16> {
+    half8 a0, a1, g;
+    half8 q[5];
+};
+template <> struct KOps<kDtBF16> {
+    bhalf8 a0, a1, g;
+    float4 q[5][2];
+};
+
+// The MFMA operands of one K step: both row blocks' A and the six B.
+// VALU instructions placed after each MFMA in the pipelined K step (F16:
+// 20 packed multiplies for 12 MFMAs; BF16 forms its products in FP32)
+template <int DT> constexpr int kHalfValu = DT == kDtF16 ? 3 : 9;
+template <int DT> struct KB {
+    typename HalfT<DT>::V8 a0, a1, b[6];
 };
 
 // Planar DQ product (c1 + s1 k + eps (x1 i + y1 j)) (c2 + s2 k + eps (x2 i +
@@ -948,17 +1056,31 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
     // ---- reference at the tile centre: FP32 blend over all inliers
     float sums[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (!bad) {
+        // eight records per thread in flight at once (indices clamped, the
+        // surplus ones weighted 0, which leaves the sums unchanged); the sums
+        // keep the order j = tid, tid + 256, ...
+        constexpr int kU = 8;
         const float nal2 = -ka * ka;
-        for (int j = tid; j < n_in; j += kFieldThreads) {
-            const float4 r0 = packed[2 * j], r1 = packed[2 * j + 1];
-            const float dx = pcx - r0.x, dy = pcy - r0.y;
-            const float wj = fast_exp2(nal2 * (dx * dx + dy * dy));
-            sums[0] += wj;
-            sums[1] += wj * r0.z;
-            sums[2] += wj * r0.w;
-            sums[3] += wj * r1.x;
-            sums[4] += wj * r1.y;
-            sums[5] += wj * r1.z;
+        for (int j0 = tid; j0 < n_in; j0 += kU * kFieldThreads) {
+            float4 r0[kU], r1[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = min(j0 + u * kFieldThreads, n_in - 1);
+                r0[u] = packed[2 * j];
+                r1[u] = packed[2 * j + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const float dx = pcx - r0[u].x, dy = pcy - r0[u].y;
+                const float e = fast_exp2(nal2 * (dx * dx + dy * dy));
+                const float wj = j0 + u * kFieldThreads < n_in ? e : 0.f;
+                sums[0] += wj;
+                sums[1] += wj * r0[u].z;
+                sums[2] += wj * r0[u].w;
+                sums[3] += wj * r1[u].x;
+                sums[4] += wj * r1[u].y;
+                sums[5] += wj * r1[u].z;
+            }
         }
     }
 #pragma unroll
@@ -1016,34 +1138,23 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
         const int gcol = 64 * (wave & 1) + lane;
         const float zxa = ka * (float)(px0 + gcol), zya = ka * (float)(py0 + lane);
         const int jx = 32 * (wave >> 1), jy = 16 * wave;
-        // With tables (gx_tab set) the factors were computed once per launch
-        // by k_half_tables: rows of tab_stride values per grid column / row
-        // of the region, zero past the inliers.
-        const T *gxt = gx_tab ? (const T *)gx_tab + (size_t)(px0 - zx0 + gcol) * tab_stride
-                              : nullptr;
-        const T *gyt = gy_tab ? (const T *)gy_tab + (size_t)(py0 - zy0 + lane) * tab_stride
-                              : nullptr;
+        // Without factor tables each chunk's factors are generated here.
         auto gen = [&](int jc, int nb, int part) {
             const int bx = __builtin_amdgcn_readfirstlane(jc + jx + 8 * part);
             const int by = __builtin_amdgcn_readfirstlane(jc + jy + 4 * part);
             V8 gxv;
             V4 gyv;
-            if (gxt) {
-                gxv = *(const V8 *)(gxt + bx);
-                gyv = *(const V4 *)(gyt + by);
-            } else {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const float d = ka * xs[bx + i] - zxa;
-                    const float e = fast_exp2(-(d * d));
-                    gxv[i] = (T)(bx + i < n_in ? e : 0.f);
-                }
+            for (int i = 0; i < 8; ++i) {
+                const float d = ka * xs[bx + i] - zxa;
+                const float e = fast_exp2(-(d * d));
+                gxv[i] = (T)(bx + i < n_in ? e : 0.f);
+            }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float d = ka * ys[by + i] - zya;
-                    const float e = fast_exp2(-(d * d));
-                    gyv[i] = (T)(by + i < n_in ? e : 0.f);
-                }
+            for (int i = 0; i < 4; ++i) {
+                const float d = ka * ys[by + i] - zya;
+                const float e = fast_exp2(-(d * d));
+                gyv[i] = (T)(by + i < n_in ? e : 0.f);
             }
             *(V8 *)&L.gx[nb][gcol][jx + 8 * part] = gxv;
             *(V4 *)&L.gy[nb][lane][jy + 4 * part] = gyv;
@@ -1064,55 +1175,93 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
                 for (int c = 0; c < 5; ++c) L.qd[nb][c][lane] = (typename HalfT<DT>::Q)v[c];
             }
         };
-        auto kstep = [&](int buf, int s) {
+        // One K step of 16 inliers: the operands (both row blocks' y factors,
+        // the x factors of the wavefront's columns, the coded node values)
+        // are read from LDS by kload, then kmma forms the B operands and
+        // issues the 12 MFMAs.  Splitting the two lets the reads of the
+        // next step be issued before the MFMAs of this one.
+        KOps<DT> cur;
+        auto kload = [&](int buf, int s, KOps<DT> &o) {
             const int k8 = 16 * s + 8 * half;
-            const V8 a0 = *(const V8 *)&L.gy[buf][col][k8];
-            const V8 a1 = *(const V8 *)&L.gy[buf][32 + col][k8];
-            const V8 g = *(const V8 *)&L.gx[buf][32 * wave + col][k8];
-            V8 bop[6];
-            if constexpr (DT == kDtF16) {
+            o.a0 = *(const V8 *)&L.gy[buf][col][k8];
+            o.a1 = *(const V8 *)&L.gy[buf][32 + col][k8];
+            o.g = *(const V8 *)&L.gx[buf][32 * wave + col][k8];
 #pragma unroll
-                for (int c = 0; c < 5; ++c) bop[c] = g * *(const half8 *)&L.qd[buf][c][k8];
-            } else {
-                float gf[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) gf[i] = (float)g[i];
-#pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    const float4 q0 = *(const float4 *)&L.qd[buf][c][k8];
-                    const float4 q1 = *(const float4 *)&L.qd[buf][c][k8 + 4];
-                    const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) bop[c][i] = (T)(gf[i] * qv[i]);
-                }
-            }
-            bop[5] = g;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
+            for (int c = 0; c < 5; ++c) {
                 if constexpr (DT == kDtF16) {
-                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, bop[c], acc[0][c], 0, 0, 0);
-                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, bop[c], acc[1][c], 0, 0, 0);
+                    o.q[c] = *(const half8 *)&L.qd[buf][c][k8];
                 } else {
-                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bop[c], acc[0][c], 0, 0, 0);
-                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bop[c], acc[1][c], 0, 0, 0);
+                    o.q[c][0] = *(const float4 *)&L.qd[buf][c][k8];
+                    o.q[c][1] = *(const float4 *)&L.qd[buf][c][k8 + 4];
                 }
             }
         };
-        if (gxt) {
-            // Tables: the next chunk's factors and node records are loaded
+        // kbuild forms the B operands B_c = gx * (coded value c) and B_5 = gx
+        auto kbuild = [&](const KOps<DT> &o, KB<DT> &k) {
+            k.a0 = o.a0;
+            k.a1 = o.a1;
+            if constexpr (DT == kDtF16) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) k.b[c] = o.g * o.q[c];
+            } else {
+                float gf[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) gf[i] = (float)o.g[i];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const float4 q0 = o.q[c][0], q1 = o.q[c][1];
+                    const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) k.b[c][i] = (T)(gf[i] * qv[i]);
+                }
+            }
+            k.b[5] = o.g;
+        };
+        auto kmfma = [&](const KB<DT> &k) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                if constexpr (DT == kDtF16) {
+                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(k.a0, k.b[c], acc[0][c], 0, 0, 0);
+                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(k.a1, k.b[c], acc[1][c], 0, 0, 0);
+                } else {
+                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(k.a0, k.b[c], acc[0][c], 0, 0, 0);
+                    acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(k.a1, k.b[c], acc[1][c], 0, 0, 0);
+                }
+            }
+        };
+        auto kmma = [&](const KOps<DT> &o) {
+            KB<DT> k;
+            kbuild(o, k);
+            kmfma(k);
+        };
+        auto kstep = [&](int buf, int s) {
+            kload(buf, s, cur);
+            kmma(cur);
+        };
+        if (gx_tab) {
+            // Tables (k_half_tables: rows of tab_stride values per grid column
+            // / row of the region, valid up to n_in rounded up to kHK, zero
+            // past n_in).  The next chunk's factors and node records are loaded
             // into registers one chunk ahead and stored to LDS after the
             // current chunk's MFMAs, so the loads' latency is hidden.
-            V8 pgx[4];
-            V4 pgy[4];
+            // A chunk's slice of a table row is 64 values = 128 B, 8 pieces
+            // of 16 B.  Workgroup thread e loads pieces e, e + 256, ... in
+            // order, so 8 consecutive lanes read one row's aligned 128 B and
+            // each load instruction touches 8 cache lines.
+            V8 pgx[kHTx * 8 / kFieldThreads], pgy[kHTy * 8 / kFieldThreads];
             float4 pr0 = make_float4(0.f, 0.f, 0.f, 0.f), pr1 = pr0;
+            const T *gxw =
+                (const T *)gx_tab + (size_t)(px0 - zx0 + tid / 8) * tab_stride + 8 * (tid % 8);
+            const T *gyw =
+                (const T *)gy_tab + (size_t)(py0 - zy0 + tid / 8) * tab_stride + 8 * (tid % 8);
+            constexpr size_t kRowStep = kFieldThreads / 8;   // rows per piece sweep
             auto fetch = [&](int jc) {
 #pragma unroll
-                for (int part = 0; part < 4; ++part) {
-                    const int bx = __builtin_amdgcn_readfirstlane(jc + jx + 8 * part);
-                    const int by = __builtin_amdgcn_readfirstlane(jc + jy + 4 * part);
-                    pgx[part] = *(const V8 *)(gxt + bx);
-                    pgy[part] = *(const V4 *)(gyt + by);
-                }
+                for (int part = 0; part < kHTx * 8 / kFieldThreads; ++part)
+                    pgx[part] = *(const V8 *)(gxw + part * kRowStep * tab_stride + jc);
+#pragma unroll
+                for (int part = 0; part < kHTy * 8 / kFieldThreads; ++part)
+                    pgy[part] = *(const V8 *)(gyw + part * kRowStep * tab_stride + jc);
                 if (wave == 3 && jc + lane < n_in) {
                     pr0 = packed[2 * (jc + lane)];
                     pr1 = packed[2 * (jc + lane) + 1];
@@ -1120,10 +1269,11 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
             };
             auto store = [&](int jc, int nb) {
 #pragma unroll
-                for (int part = 0; part < 4; ++part) {
-                    *(V8 *)&L.gx[nb][gcol][jx + 8 * part] = pgx[part];
-                    *(V4 *)&L.gy[nb][lane][jy + 4 * part] = pgy[part];
-                }
+                for (int part = 0; part < kHTx * 8 / kFieldThreads; ++part)
+                    *(V8 *)&L.gx[nb][part * kRowStep + tid / 8][8 * (tid % 8)] = pgx[part];
+#pragma unroll
+                for (int part = 0; part < kHTy * 8 / kFieldThreads; ++part)
+                    *(V8 *)&L.gy[nb][part * kRowStep + tid / 8][8 * (tid % 8)] = pgy[part];
                 if (wave == 3) {
                     float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
                     if (jc + lane < n_in) {
@@ -1139,19 +1289,55 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
                     for (int c = 0; c < 5; ++c) L.qd[nb][c][lane] = (typename HalfT<DT>::Q)v[c];
                 }
             };
+            // Chunk c lives in buffer c % 3.  Iteration c multiplies chunk c,
+            // stores chunk c + 2 (into the buffer chunk c - 1 used, free
+            // since the previous barrier) and fetches chunk c + 3; chunk
+            // c + 1 was stored before the previous barrier, so its first K
+            // step is read while chunk c's last MFMAs run.
             fetch(0);
             store(0, 0);
-            if (nchunks > 1) fetch(kHK);
+            if (nchunks > 1) {
+                fetch(kHK);
+                store(kHK, 1);
+            }
+            if (nchunks > 2) fetch(2 * kHK);
             __syncthreads();
+            // Software pipeline over K steps: step t issues the LDS reads of
+            // step t + 1, then its own 12 MFMAs (operands formed during step
+            // t - 1) interleaved with forming step t + 1's B operands, so
+            // a single wavefront keeps the MFMA pipe fed.  The last step of a
+            // chunk reads step 0 of the next chunk's buffer (after the last
+            // chunk that is a stale buffer, read in bounds and never used).
+            KB<DT> bcur, bnxt;
+            kload(0, 0, cur);
+            kbuild(cur, bcur);
+            int buf = 0;
             for (int c = 0; c < nchunks; ++c) {
-                const int buf = c & 1;
+                const int nbuf = buf == 2 ? 0 : buf + 1;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) kstep(buf, s);
-                if (c + 1 < nchunks) {
-                    store((c + 1) * kHK, buf ^ 1);
-                    if (c + 2 < nchunks) fetch((c + 2) * kHK);
+                for (int s = 0; s < 4; ++s) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    kload(s < 3 ? buf : nbuf, (s + 1) & 3, cur);
+                    kmfma(bcur);
+                    kbuild(cur, bnxt);
+                    // 8 LDS reads, 4 MFMAs (the reads land), then one MFMA
+                    // per kHalfValu VALU instructions
+                    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+#pragma unroll
+                    for (int g = 0; g < 8; ++g) {
+                        __builtin_amdgcn_sched_group_barrier(0x002, kHalfValu<DT>, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    bcur = bnxt;
+                }
+                if (c + 2 < nchunks) {
+                    store((c + 2) * kHK, nbuf == 2 ? 0 : nbuf + 1);
+                    if (c + 3 < nchunks) fetch((c + 3) * kHK);
                 }
                 __syncthreads();
+                buf = nbuf;
             }
         } else {
 #pragma unroll
@@ -1170,14 +1356,22 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
         }
     }
 
-    // ---- epilogue: undo the coding, DQ normalisation, Eq. (1)
+    // ---- epilogue: undo the coding, DQ normalisation, Eq. (1); the warp
+    // merges the pixels in groups of kHGroup
+    constexpr int kHGroup = 8;
+    int pzx[kHGroup], pzy[kHGroup];
+    float2 pd[kHGroup];
+    bool live[kHGroup];
 #pragma unroll
     for (int bl = 0; bl < 2; ++bl)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int zx = px0 + 32 * wave + col;
         const int zy = py0 + 32 * bl + 8 * (r >> 2) + 4 * half + (r & 3);
-        if (zx >= zx0 + w || zy >= zy0 + h) continue;
+        const int gi = r % kHGroup;
+        pzx[gi] = zx;
+        pzy[gi] = zy;
+        live[gi] = zx < zx0 + w && zy < zy0 + h;
         const float W = acc[bl][5][r];
         const float C = acc[bl][0][r] + W, S = acc[bl][1][r];
         const float X = acc[bl][2][r], Y = acc[bl][3][r];
@@ -1191,49 +1385,63 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
         const float sg = sm1 + acc[bl][4][r] / W;
         const float fzx = (float)zx, fzy = (float)zy;
         const float2 d = make_float2(ex + sg * (fzx + ex), ey + sg * (fzy + ey));
+        pd[gi] = d;
         if constexpr (MODE == kModeField) {
-            out[(size_t)(zy - zy0) * opitch + (zx - zx0)] =
-                bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
-                    : make_float2(fzx + d.x, fzy + d.y);
-        } else {
-            warp_merge(zx, zy, d, frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
+            if (live[gi])
+                out[(size_t)(zy - zy0) * opitch + (zx - zx0)] =
+                    bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
+                        : make_float2(fzx + d.x, fzy + d.y);
+        } else if constexpr (!EMDQ_WARP_BATCH) {
+            if (live[gi]) warp_merge(zx, zy, d, frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
+        } else if (gi == kHGroup - 1) {
+            warp_merge_batch<kHGroup>(pzx, pzy, pd, live, zx0, zy0, frame, fw, fh, fpitch, canvas,
+                                      cpitch, ox, oy);
         }
     }
 }
 
 // Per-axis Gaussian factors of the half-precision blend, once per launch:
-// row c of the x table holds gx(zx0 + c, j) = exp(-alpha (zx0 + c - x_j)^2)
-// for j < tab_stride (zero for j >= n_in), row r of the y table likewise for
-// zy0 + r.  One thread writes eight consecutive j of one row.
+// row c of the x table holds gx(zx0 + c, j) = exp(-alpha (zx0 + c - x_j)^2),
+// row r of the y table likewise for zy0 + r.  Each thread loads eight
+// consecutive coordinates x_j once and writes them into kTabRowsPer rows
+// (workgroup row blockIdx.y covers rows [kTabRowsPer blockIdx.y, +kTabRowsPer),
+// x rows first; both row counts are multiples of kTabRowsPer).  Only j below
+// n_in rounded up to the blend's K chunk is written (zero for j >= n_in): the
+// blend reads no further.
+constexpr int kTabRowsPer = 16;
+static_assert(kHTx % kTabRowsPer == 0 && kHTy % kTabRowsPer == 0, "table row blocks");
 template <int DT>
 __global__ __launch_bounds__(256) void k_half_tables(
     const float *__restrict__ xs, const float *__restrict__ ys,
-    const DevState *__restrict__ st, float ka, int zx0, int zy0, int rows_x, int rows_y,
-    int tab_stride, void *__restrict__ gx_tab, void *__restrict__ gy_tab) {
+    const DevState *__restrict__ st, float ka, int zx0, int zy0, int rows_x, int tab_stride,
+    void *__restrict__ gx_tab, void *__restrict__ gy_tab) {
     using T = typename HalfT<DT>::T;
     using V8 = typename HalfT<DT>::V8;
     const int n_in = st->status < 0 ? 0 : st->n_in;
-    const int per_row = tab_stride / 8;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long long)(rows_x + rows_y) * per_row) return;
-    const int row = (int)(e / per_row), j0 = 8 * (int)(e % per_row);
-    const bool is_x = row < rows_x;
-    const int r = is_x ? row : row - rows_x;
-    const float za = ka * (float)(is_x ? zx0 + r : zy0 + r);
+    const int lim = min(tab_stride, (n_in + kHK - 1) / kHK * kHK);
+    const int j0 = 8 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j0 >= lim) return;
+    const int row0 = kTabRowsPer * (int)blockIdx.y;
+    const bool is_x = row0 < rows_x;
+    const int r0 = is_x ? row0 : row0 - rows_x;
     const float *src = is_x ? xs : ys;
-    V8 v;
+    // all eight loads in flight at once (n_in >= 1 here; indices clamped)
+    float c[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int j = j0 + i;
-        float g = 0.f;
-        if (j < n_in) {
-            const float d = ka * src[j] - za;
-            g = fast_exp2(-(d * d));
+    for (int i = 0; i < 8; ++i) c[i] = ka * src[min(j0 + i, n_in - 1)];
+    T *dst = (T *)(is_x ? gx_tab : gy_tab) + (size_t)r0 * tab_stride + j0;
+    const int z0 = (is_x ? zx0 : zy0) + r0;
+#pragma unroll 4
+    for (int k = 0; k < kTabRowsPer; ++k) {
+        const float za = ka * (float)(z0 + k);
+        V8 v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float d = c[i] - za;
+            v[i] = (T)(j0 + i < n_in ? fast_exp2(-(d * d)) : 0.f);
         }
-        v[i] = (T)g;
+        *(V8 *)(dst + (size_t)k * tab_stride) = v;
     }
-    T *dst = (T *)(is_x ? gx_tab : gy_tab) + (size_t)r * tab_stride + j0;
-    *(V8 *)dst = v;
 }
 
 // ---------------------------------------------- node tracking, uncertainty ----
@@ -1805,7 +2013,7 @@ __global__ void k_gather_states(const EmJob *__restrict__ jobs, int n_pairs,
 }
 
 template <int MODE, int SPLITK>
-__global__ __launch_bounds__(kFieldThreads) void k_field_b(const FieldJob *__restrict__ jobs,
+__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(kFieldWaves, kFieldWaves))) void k_field_b(const FieldJob *__restrict__ jobs,
                                                            int n_jobs) {
     int lo = 0, hi = n_jobs - 1;   // last job whose first workgroup is <= blockIdx.x
     while (lo < hi) {
@@ -1896,16 +2104,16 @@ emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h,
                 const int hx = (sw + kHTx - 1) / kHTx, hy = (sh + kHTy - 1) / kHTy;
                 const int zx = zx0 + sx, zy = zy0 + sy;
                 if (gxt) {
-                    const long long elems = (long long)(hx * kHTx + hy * kHTy) * (m->tab_stride / 8);
-                    const unsigned tb = (unsigned)((elems + 255) / 256);
+                    const dim3 tg((unsigned)((m->tab_stride / 8 + 255) / 256),
+                                  (unsigned)((hx * kHTx + hy * kHTy) / kTabRowsPer));
                     if (f16)
-                        hipLaunchKernelGGL(k_half_tables<kDtF16>, dim3(tb), dim3(256), 0, stream,
+                        hipLaunchKernelGGL(k_half_tables<kDtF16>, tg, dim3(256), 0, stream,
                                            m->xs, m->ys, m->st, ka, zx, zy, hx * kHTx,
-                                           hy * kHTy, m->tab_stride, gxt, gyt);
+                                           m->tab_stride, gxt, gyt);
                     else
-                        hipLaunchKernelGGL(k_half_tables<kDtBF16>, dim3(tb), dim3(256), 0,
-                                           stream, m->xs, m->ys, m->st, ka, zx, zy, hx * kHTx,
-                                           hy * kHTy, m->tab_stride, gxt, gyt);
+                        hipLaunchKernelGGL(k_half_tables<kDtBF16>, tg, dim3(256), 0, stream,
+                                           m->xs, m->ys, m->st, ka, zx, zy, hx * kHTx,
+                                           m->tab_stride, gxt, gyt);
                 }
                 // the slab's outputs are addressed through its own origin
                 const unsigned nb = (unsigned)(hx * hy);
