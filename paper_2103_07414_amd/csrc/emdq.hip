@@ -1017,6 +1017,11 @@ template <> struct KOps<kDtBF16> {
 // VALU instructions placed after each MFMA in the pipelined K step (F16:
 // 20 packed multiplies for 12 MFMAs; BF16 forms its products in FP32)
 template <int DT> constexpr int kHalfValu = DT == kDtF16 ? 3 : 9;
+#ifndef EMDQ_HALF_LEAD
+#define EMDQ_HALF_LEAD 6
+#endif
+// MFMAs of a K step issued before the first VALU that waits on its LDS reads
+constexpr int kHalfLead = EMDQ_HALF_LEAD;
 template <int DT> struct KB {
     typename HalfT<DT>::V8 a0, a1, b[6];
 };
@@ -1323,9 +1328,9 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
                     // 8 LDS reads, 4 MFMAs (the reads land), then one MFMA
                     // per kHalfValu VALU instructions
                     __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, kHalfLead, 0);
 #pragma unroll
-                    for (int g = 0; g < 8; ++g) {
+                    for (int g = 0; g < 12 - kHalfLead; ++g) {
                         __builtin_amdgcn_sched_group_barrier(0x002, kHalfValu<DT>, 0);
                         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
                     }
