@@ -505,8 +505,16 @@ constexpr int kPostThreads = 1024;
 __device__ __forceinline__ void posterior_body(
     float *__restrict__ p, const float *__restrict__ e2, uint8_t *__restrict__ mask, int n,
     double u, double sigma2_min, double gamma_min, double gamma_max, float p_thresh,
-    int max_iter, DevState *st, int block) {
-    if (st->status < 0 || st->done) return;
+    int max_iter, DevState *st, DevState *host_copy, int block) {
+    // host_copy (pinned host memory, may be null): the state as this kernel
+    // leaves it, so the host reads the stop flag without a copy
+    auto publish = [&]() {
+        if (host_copy && threadIdx.x == 0) *host_copy = *st;
+    };
+    if (st->status < 0 || st->done) {
+        publish();
+        return;
+    }
     __shared__ double red_p[kPostThreads], red_pe[kPostThreads];
     __shared__ int any_changed;
     if (threadIdx.x == 0) any_changed = 0;
@@ -532,6 +540,7 @@ __device__ __forceinline__ void posterior_body(
             st->status = EMDQ_ENOINLIERS;
             st->done = 1;
         }
+        publish();
         return;
     }
     double sigma2 = SPE / (2.0 * SP);
@@ -565,13 +574,15 @@ __device__ __forceinline__ void posterior_body(
             st->status = EMDQ_WARN_NOT_CONVERGED;
         }
     }
+    publish();
 }
 
 __global__ __launch_bounds__(kPostThreads) void k_posterior(
     float *__restrict__ p, const float *__restrict__ e2, uint8_t *__restrict__ mask, int n,
     double u, double sigma2_min, double gamma_min, double gamma_max, float p_thresh,
-    int max_iter, DevState *st) {
-    posterior_body(p, e2, mask, n, u, sigma2_min, gamma_min, gamma_max, p_thresh, max_iter, st, blockIdx.x);
+    int max_iter, DevState *st, DevState *host_copy) {
+    posterior_body(p, e2, mask, n, u, sigma2_min, gamma_min, gamma_max, p_thresh, max_iter, st,
+                   host_copy, blockIdx.x);
 }
 
 // ------------------------------------------------------------ compaction ----
@@ -2003,7 +2014,7 @@ __global__ __launch_bounds__(kPostThreads) void k_posterior_b(
     float p_thresh, int max_iter) {
     const EmJob &J = jobs[blockIdx.x];
     posterior_body(J.p, J.e2, J.mask, J.n, J.u, sigma2_min, gamma_min, gamma_max, p_thresh,
-                   max_iter, J.st, 0);
+                   max_iter, J.st, nullptr, 0);
 }
 
 __global__ __launch_bounds__(kCompactThreads) void k_compact_b(const EmJob *__restrict__ jobs) {
@@ -2056,6 +2067,7 @@ struct emdq_model_s {
     DevState *st = nullptr;
     DevState *host_st = nullptr;   // pinned
     DevState *em_st = nullptr;     // pinned [2]: stop flags read while the EM runs on
+    DevState *em_st_dev = nullptr; // the same two slots, as the device addresses them
     hipEvent_t em_ev[2] = {};
     hipStream_t last = nullptr;
 };
@@ -2214,8 +2226,10 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     ok = ok && hipMalloc((void **)&m->st, sizeof(DevState)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&m->host_st, sizeof(DevState), hipHostMallocDefault) ==
                    hipSuccess;
-    ok = ok && hipHostMalloc((void **)&m->em_st, 2 * sizeof(DevState), hipHostMallocDefault) ==
+    // coherent: the posterior kernel stores the stop flags straight into them
+    ok = ok && hipHostMalloc((void **)&m->em_st, 2 * sizeof(DevState), hipHostMallocCoherent) ==
                    hipSuccess;
+    ok = ok && hipHostGetDevicePointer((void **)&m->em_st_dev, m->em_st, 0) == hipSuccess;
     for (int k = 0; ok && k < 2; ++k)
         ok = hipEventCreateWithFlags(&m->em_ev[k], hipEventDisableTiming) == hipSuccess;
     if (ok) {
@@ -2300,17 +2314,20 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
     // GPU does not wait for the host between chunks.
     int enqueued = 0;
     for (int k = 0;; ++k) {
+        // the chunk's last posterior also stores the state into host slot
+        // k & 1 (a chunk holds at least one iteration: the loop leaves once
+        // max_iter iterations are enqueued)
         for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
+            const bool last = c + 1 == kEmChunk || enqueued + 1 == prm.max_iter;
             mstep(0);
             hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
                                m->p, m->q, m->s, n, nal2, m->e2, m->st);
             hipLaunchKernelGGL(k_posterior, dim3(1), dim3(kPostThreads), 0, stream, m->p, m->e2,
                                m->mask, n, u, (double)prm.sigma2_min, (double)prm.gamma_min,
-                               (double)prm.gamma_max, prm.p_thresh, prm.max_iter, m->st);
+                               (double)prm.gamma_max, prm.p_thresh, prm.max_iter, m->st,
+                               last ? &m->em_st_dev[k & 1] : nullptr);
         }
         if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
-        EMDQ_HIP(hipMemcpyAsync(&m->em_st[k & 1], m->st, sizeof(DevState),
-                                hipMemcpyDeviceToHost, stream));
         EMDQ_HIP(hipEventRecord(m->em_ev[k & 1], stream));
         if (k > 0) {
             EMDQ_HIP(hipEventSynchronize(m->em_ev[(k - 1) & 1]));
