@@ -38,8 +38,14 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kWave = 64;
 constexpr int kRowsPerBlock = 8;        // EM kernels: one wavefront per match
 constexpr int kEmThreads = kWave * kRowsPerBlock;
-constexpr int kMChunk = 2048;           // matches staged in LDS per M-step sweep
-constexpr int kEChunk = 1024;           // matches (+ fits) staged per E-step sweep
+#ifndef EMDQ_MCHUNK
+#define EMDQ_MCHUNK 2048
+#endif
+#ifndef EMDQ_ECHUNK
+#define EMDQ_ECHUNK 1024
+#endif
+constexpr int kMChunk = EMDQ_MCHUNK;    // matches staged in LDS per M-step sweep
+constexpr int kEChunk = EMDQ_ECHUNK;    // matches (+ fits) staged per E-step sweep
 constexpr int kCompactThreads = 1024;
 constexpr int kFieldThreads = 256;      // 4 wavefronts per workgroup
 constexpr int kTile = 32;               // 32 x 32 pixels per MFMA output tile

@@ -170,3 +170,41 @@ def test_half_field_in_slabs_matches_oracle():
     err = np.abs(got[:, near] - want[:, near]).max()
     print(f"slab field max err {err:.2e} px over {near.sum()} columns", flush=True)
     assert err <= HALF_TOL_PX["f16"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+def test_field_small_inlier_counts(prec):
+    """Inlier counts around the blend's chunk of 64 (one to four chunks,
+    ragged and exact): the oracle's nodes of a production pair with the mask
+    cut to the n_keep inliers nearest the region, every pixel of a ragged
+    300 x 201 region at the frame centre.  (The kept nodes lie within a few
+    hundred px of every pixel, where the FP16 per-axis factors do not
+    underflow.)"""
+    torch = torch_or_skip()
+    E = emdq()
+    P = synth.gen_config(2, 1, with_frame=False)
+    ref = oracle_fit(P)
+    W, H = P.cfg.width, P.cfg.height
+    zx0, zy0, w, h = W // 2 - 150, H // 2 - 100, 300, 201
+    centre = np.array([zx0 + w / 2, zy0 + h / 2])
+    inl = np.flatnonzero(ref.mask)
+    order = inl[np.argsort(np.linalg.norm(P.src[inl] - centre, axis=1), kind="stable")]
+    s32 = ref.scale.astype(np.float32)
+    q32 = ref.q.astype(np.float32)
+    tol = 1e-3 if prec == "f32" else HALF_TOL_PX[prec]
+    m = E.Model(P.cfg.n_matches)
+    if prec != "f32":
+        m.set_precision(prec)
+    out = torch.empty((h, w, 2), dtype=torch.float32, device="cuda")
+    for n_keep in (1, 37, 64, 65, 128, 129, 192, 193, 255):
+        mask = np.zeros_like(ref.mask)
+        mask[order[:n_keep]] = 1
+        m.set_nodes(P.src, s32, q32, mask, ref.alpha)
+        m.field(zx0, zy0, w, h, out)
+        rc, want = O.field(P.src, s32.astype(np.float64), q32.astype(np.float64), mask,
+                           float(np.float32(ref.alpha)), zx0, zy0, w, h)
+        err = np.abs(out.cpu().numpy() - want).max()
+        print(f"{prec} n_in {n_keep}: field max err {err:.2e} px", flush=True)
+        assert m.results()["n_in"] == n_keep
+        assert rc == 0 and err <= tol, (prec, n_keep, err)
+    m.close()
