@@ -189,7 +189,7 @@ def plain_sequential(E, torch, pairs, srcs, dsts, frames, canvases, layouts, siz
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
