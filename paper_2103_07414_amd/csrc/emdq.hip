@@ -7,13 +7,18 @@
 //
 // Kernels
 //   k_reset / k_load   model state reset; copy of the matches, finiteness check
-//   k_mstep            per-match weighted similarity fit (Eqs. (18)-(20)) with
+//   k_mstep            posterior step of the previous iteration (FP64
+//                      fixed-order sums, posteriors, inlier mask), then the
+//                      per-match weighted similarity fit (Eqs. (18)-(20)) with
 //                      weights exp(-alpha d^2) p_j (Eq. (4)); one wavefront per
 //                      match, lanes stride the other matches, two-pass
 //                      centred FP32 moments, FP64 re-fit of near-degenerate rows
-//   k_estep            DQ blend at every match (Eqs. (2)-(3)), residuals
-//   k_posterior        one workgroup: FP64 fixed-order reduction, posteriors,
-//                      inlier mask and the stop flag
+//   k_estep            stop rule of the previous iteration; DQ blend at every
+//                      match (Eqs. (2)-(3)), residuals, per-workgroup sums
+//   k_mstep_s, k_estep_s, k_posterior
+//                      the same EM in three launches per iteration (above
+//                      kFusedMaxN matches): the posterior step and the stop
+//                      rule in a one-workgroup kernel of their own
 //   k_compact          packs the inliers for the field kernel (one workgroup,
 //                      ordered scan)
 //   k_field<MODE>      the W(P x N_in) . Q(N_in x 6) blend on FP32 MFMA, with
@@ -78,6 +83,10 @@ constexpr int kFieldWaves = EMDQ_FIELD_WAVES;
 #define EMDQ_EM_CHUNK 2
 #endif
 constexpr int kEmChunk = EMDQ_EM_CHUNK; // EM iterations enqueued between stop-flag reads
+#ifndef EMDQ_FUSED_MAX_N
+#define EMDQ_FUSED_MAX_N 2048
+#endif
+constexpr int kFusedMaxN = EMDQ_FUSED_MAX_N;   // single-pair fits: two launches per iteration up to this n
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -91,6 +100,7 @@ struct DevState {
     int changed;     // mask changed in the last iteration
     float sigma2;
     float gamma;
+    int stop_at;     // single-pair fit: launch that ended the EM (em_stopped), 0 = running
 };
 
 // ------------------------------------------------------------ helpers ----
@@ -129,6 +139,17 @@ __device__ __forceinline__ void reset_state(DevState *st) {
     st->changed = 0;
     st->sigma2 = 0.f;
     st->gamma = 0.f;
+    st->stop_at = 0;
+}
+
+// The launches of a single-pair fit, numbered in enqueue order: the load is 1,
+// iteration it (from 1) is the M-step 2 it and then the E-step 2 it + 1.  The
+// launch that ends the EM stores its own number in stop_at with one 32-bit
+// store, so a workgroup of that same launch reads either 0 or the launch's
+// own number and carries on; every later launch returns at once.
+constexpr int kOrdLoad = 1;
+__device__ __forceinline__ bool em_stopped(int stop_at, int ordinal) {
+    return stop_at != 0 && stop_at < ordinal;
 }
 
 __global__ void k_reset(DevState *st) {
@@ -149,6 +170,7 @@ __device__ __forceinline__ void load_body(const float2 *__restrict__ src, const 
     if (!finite2(a) || !finite2(b)) {
         atomicMin(&st->status, (int)EMDQ_ENONFINITE);
         atomicExch(&st->done, 1);
+        atomicExch(&st->stop_at, kOrdLoad);
     }
 }
 
@@ -169,36 +191,138 @@ __global__ void k_load(const float2 *__restrict__ src, const float2 *__restrict_
 //   D = sg z + (1 + sg) ((R_hat - I) z + t_hat),
 // where c, sn, x, y, sg are the weighted means of q_c, q_s, q_x, q_y, s - 1.
 // Nothing large cancels, so FP32 keeps ~1e-5 px on a ~1000 px coordinate.
+// Contraction is off in the EM arithmetic and in this function: every fused
+// multiply-add is written out, so each kernel that inlines the code rounds
+// exactly alike (batched and single-pair fits agree bit for bit).
 __device__ __forceinline__ float2 blend_displacement(float W, float Cd, float Sn, float X, float Y,
                                                      float Gd, float zx, float zy) {
+#pragma clang fp contract(off)
     const float iW = 1.f / W;
-    const float c = 1.f + Cd * iW, sn = Sn * iW, x = X * iW, y = Y * iW, sg = Gd * iW;
-    const float in2 = 1.f / (c * c + sn * sn);
+    const float c = __builtin_fmaf(Cd, iW, 1.f), sn = Sn * iW, x = X * iW, y = Y * iW,
+                sg = Gd * iW;
+    const float in2 = 1.f / __builtin_fmaf(c, c, sn * sn);
     const float r00 = -2.f * sn * sn * in2, r10 = 2.f * c * sn * in2;
-    const float tx = 2.f * (c * x - sn * y) * in2, ty = 2.f * (c * y + sn * x) * in2;
+    const float tx = 2.f * __builtin_fmaf(c, x, -(sn * y)) * in2,
+                ty = 2.f * __builtin_fmaf(c, y, sn * x) * in2;
     const float s1 = 1.f + sg;
-    return make_float2(sg * zx + s1 * (r00 * zx - r10 * zy + tx),
-                       sg * zy + s1 * (r10 * zx + r00 * zy + ty));
+    return make_float2(
+        __builtin_fmaf(sg, zx, s1 * (__builtin_fmaf(r00, zx, -(r10 * zy)) + tx)),
+        __builtin_fmaf(sg, zy, s1 * (__builtin_fmaf(r10, zx, r00 * zy) + ty)));
+}
+
+// ------------------------------------------------------------ posterior ----
+//
+// Gaussian-inlier / uniform-outlier mixture of Sec. II-A.  Each E-step
+// workgroup leaves, for its rows, the FP64 sums (sum p_i, sum p_i e_i^2) in
+// row order; sum_partials adds them over the workgroups in a fixed order, so
+// every workgroup that finishes the iteration gets the same sigma^2 and gamma
+// and hence the same posteriors.
+
+struct PostParams {
+    double u, sigma2_min, gamma_min, gamma_max;
+    float p_thresh;
+    int max_iter;
+};
+
+// p = a / (a + b), a = gamma exp(-e^2 / (2 sigma^2)) / (2 pi sigma^2),
+// b = (1 - gamma) u (FP64)
+struct PostCoef {
+    double gamma, inv2s, norm, b;
+};
+
+// Every FP64 operation of the posterior step is rounded on its own
+// (contraction off), so the kernels that inline it agree bit for bit.
+__device__ __forceinline__ float post_p(float e2, const PostCoef &c) {
+#pragma clang fp contract(off)
+    const double a = c.gamma * exp(-(double)e2 * c.inv2s) * c.norm;
+    return (float)(a / (a + c.b));
+}
+
+// Fixed-order sum of the E-step partials part[0, nb): thread t < kEmThreads
+// adds part[t], part[t + kEmThreads], ... (partial_run); a butterfly per
+// wavefront; then the first kRowsPerBlock wavefronts in order
+// (combine_partials).  Every thread of a workgroup of at least kEmThreads
+// threads calls both and gets the same bits, whichever workgroup and kernel
+// it runs in.
+// first: part[min(t, nb - 1)], loaded by the caller (so that the load can be
+// issued early, unconditionally and in bounds)
+__device__ __forceinline__ double2 partial_run(const double2 *__restrict__ part, int nb,
+                                               double2 first) {
+    const int t = threadIdx.x;
+    double2 r = make_double2(0.0, 0.0);
+    if (t < kEmThreads && t < nb) {
+        r = first;   // 0 + part[t], exactly (the sums are not negative)
+        for (int b = t + kEmThreads; b < nb; b += kEmThreads) {
+            const double2 v = part[b];
+            r.x += v.x;
+            r.y += v.y;
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ double2 combine_partials(double2 run) {
+    __shared__ double2 s_w[kRowsPerBlock];
+    const int t = threadIdx.x;
+    const double sp = wave_sum_d(run.x), spe = wave_sum_d(run.y);
+    if (t < kEmThreads && (t & (kWave - 1)) == 0) s_w[t / kWave] = make_double2(sp, spe);
+    __syncthreads();
+    double2 r = s_w[0];
+    for (int w = 1; w < kRowsPerBlock; ++w) {
+        r.x += s_w[w].x;
+        r.y += s_w[w].y;
+    }
+    return r;
+}
+
+// sigma^2 and gamma from the sums (clamped as the parameters say) and the
+// posterior coefficients; false if no posterior weight is left.
+__device__ __forceinline__ bool post_coef(double2 S, int n, const PostParams &pp,
+                                          double *sigma2_out, PostCoef *c) {
+#pragma clang fp contract(off)
+    if (!(S.x > 0.0)) return false;
+    double sigma2 = S.y / (2.0 * S.x);
+    if (!(sigma2 >= pp.sigma2_min)) sigma2 = pp.sigma2_min;
+    double gamma = S.x / (double)n;
+    gamma = gamma < pp.gamma_min ? pp.gamma_min : (gamma > pp.gamma_max ? pp.gamma_max : gamma);
+    c->gamma = gamma;
+    c->inv2s = 1.0 / (2.0 * sigma2);
+    c->norm = 1.0 / (6.283185307179586 * sigma2);
+    c->b = (1.0 - gamma) * pp.u;
+    *sigma2_out = sigma2;
+    return true;
+}
+
+// The stop rule after the posteriors of iteration it: no mask change from
+// the iteration before (from the second iteration on), or max_iter reached.
+// Returns 0 (go on), 1 (converged) or 2 (not converged by max_iter).
+__device__ __forceinline__ int stop_rule(int it, int any_changed, int max_iter) {
+    if (it >= 2 && !any_changed) return 1;
+    return it >= max_iter ? 2 : 0;
 }
 
 // --------------------------------------------------------------- M-step ----
 
 // Planar DQ from the half-angle direction (ch, sh) and the translation.
 __device__ __forceinline__ float4 dq_make(float ch, float sh, float tx, float ty) {
-    return make_float4(ch, sh, 0.5f * (ch * tx + sh * ty), 0.5f * (ch * ty - sh * tx));
+#pragma clang fp contract(off)
+    return make_float4(ch, sh, 0.5f * __builtin_fmaf(ch, tx, sh * ty),
+                       0.5f * __builtin_fmaf(ch, ty, -(sh * tx)));
 }
 
 // FP64 fit of one match, taken when the FP32 moments are too ill-conditioned
 // to decide the degenerate case: two-pass centred sums over all matches,
-// spread over the lanes of the wavefront.
-__device__ void fit_row_f64(int i, const float4 *__restrict__ xy, const float *__restrict__ p,
+// spread over the lanes of the wavefront.  p(j) gives the posterior of match j.
+template <class PostOf>
+__device__ void fit_row_f64(int i, const float4 *__restrict__ xy, const PostOf &p,
                             int n, double alpha, int lane, float *scale_out, float4 *q_out) {
+#pragma clang fp contract(off)
     const float4 me = xy[i];
     double S = 0, ax = 0, ay = 0, bx = 0, by = 0;
     for (int j = lane; j < n; j += kWave) {
         float4 v = xy[j];
         double dx = (double)v.x - me.x, dy = (double)v.y - me.y;
-        double w = exp(-alpha * (dx * dx + dy * dy)) * (double)p[j];
+        double w = exp(-alpha * (dx * dx + dy * dy)) * (double)p(j);
         S += w;
         ax += w * v.x;
         ay += w * v.y;
@@ -220,7 +344,7 @@ __device__ void fit_row_f64(int i, const float4 *__restrict__ xy, const float *_
     for (int j = lane; j < n; j += kWave) {
         float4 v = xy[j];
         double dx = (double)v.x - me.x, dy = (double)v.y - me.y;
-        double w = exp(-alpha * (dx * dx + dy * dy)) * (double)p[j];
+        double w = exp(-alpha * (dx * dx + dy * dy)) * (double)p(j);
         double a0 = v.x - mx, a1 = v.y - my, b0 = v.z - nx, b1 = v.w - ny;
         c00 += w * b0 * a0;
         c01 += w * b0 * a1;
@@ -261,34 +385,75 @@ __device__ void fit_row_f64(int i, const float4 *__restrict__ xy, const float *_
                          (float)(0.5 * (ch * ty - sh * tx)));
 }
 
+// How an EM kernel runs.  kEmBatch: pairs of a batch; the stop flag is read
+// first, so a pair that has stopped costs no loads.  kEmSingle: one pair,
+// three launches per iteration (M-step, E-step, posterior kernel).
+// kEmFused: one pair, two launches per iteration (below).  Both single-pair
+// modes issue their first loads before they wait on the stop flag.
+enum EmMode { kEmBatch = 0, kEmSingle = 1, kEmFused = 2 };
+
+// A fused single-pair fit finishes the previous iteration at the start of its
+// M-step (so an EM iteration is two launches): every workgroup sums the
+// E-step partials, forms sigma^2, gamma and the posteriors of all matches
+// (the same bits in every workgroup) and uses them as its weights; it stores
+// the posteriors and the mask of its own rows and whether any of those mask
+// bits changed.  The next E-step applies the stop rule from those flags.
+struct EmFused {
+    const float *e2;        // residuals of the previous E-step
+    const double2 *part;    // its per-workgroup sums (sum p, sum p e^2)
+    float *p_out;           // posteriors (own rows stored)
+    uint8_t *mask;          // inlier mask (own rows stored)
+    int *chg;               // per workgroup: a mask bit of its rows changed
+    PostParams pp;
+    int nb;                 // workgroups of the EM launches
+    int it;                 // this iteration (from 1); posteriors of it - 1
+};
+
 // One wavefront per match i: weights w_j = exp(-alpha |x_j - x_i|^2) p_j.
 // The workgroup stages the matches in LDS (coalesced, kMChunk at a time) and
 // each wavefront sweeps them from there.  Pass 1: weight sum and weighted
 // centroids, relative to (x_i, y_i).  Pass 2 (weights recomputed): centred
 // cross-covariance terms and spreads, so no moment is formed by cancellation.
-// Then the closed-form 2D Procrustes fit.
+// Then the closed-form 2D Procrustes fit.  kEmFused: the posterior step first
+// (EmFused); otherwise the posteriors are read from p.
+template <int kMode>
 __device__ __forceinline__ void mstep_body(
-    const float4 *__restrict__ xy, const float *__restrict__ p, int n, float nal2,
+    const float4 *__restrict__ xy, const float *p, int n, float nal2,
     double alpha, float4 *__restrict__ q_out, float *__restrict__ s_out,
-    const DevState *__restrict__ st, int final_pass, int block) {
+    DevState *st, int final_pass, const EmFused &F, int block) {
+#pragma clang fp contract(off)
     __shared__ float4 s_xy[kMChunk];
     __shared__ float s_p[kMChunk];
-    if (st->status < 0) return;
-    if (!final_pass && st->done) return;
+    if (kMode == kEmBatch) {
+        if (st->status < 0) return;
+        if (!final_pass && st->done) return;
+    }
     const int lane = threadIdx.x & (kWave - 1);
     const int i = block * kRowsPerBlock + (threadIdx.x >> 6);
     const bool active = i < n;
-    const float4 me = active ? xy[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const bool resident = n <= kMChunk;   // one staging serves both passes
-    auto stage = [&](int c0, int cn) {
-        constexpr int kPer = kMChunk / kEmThreads;
-        float4 v[kPer];
-        float pv[kPer];
+    const bool post = kMode == kEmFused && F.it >= 2;   // posteriors from F.e2 instead of p
+    // staging: a chunk's loads into registers, then (posteriors formed) LDS
+    constexpr int kPer = kMChunk / kEmThreads;
+    float4 v[kPer];
+    float r[kPer];   // e2 (post) or p of the staged matches
+    auto load_chunk = [&](int c0, int cn) {
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int t = threadIdx.x + k * kEmThreads;
-            if (t < cn) { v[k] = xy[c0 + t]; pv[k] = p[c0 + t]; }
+            if (t < cn) {
+                v[k] = xy[c0 + t];
+                r[k] = post ? F.e2[c0 + t] : p[c0 + t];
+            } else {
+                v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                r[k] = 0.f;
+            }
         }
+    };
+    PostCoef pc{};
+    auto store_chunk = [&](int cn) {
+        float pv[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) pv[k] = post ? post_p(r[k], pc) : r[k];
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
@@ -297,6 +462,61 @@ __device__ __forceinline__ void mstep_body(
         }
         __syncthreads();
     };
+    // single pair: every load of the first chunk (and of the posterior step)
+    // is issued, unconditionally and in bounds, before the stop flag (loaded
+    // last, so that one wait covers them all); the posterior loads are unused
+    // when it = 1
+    const float4 me = active ? xy[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    double2 run = make_double2(0.0, 0.0);
+    float e2_own = 0.f;
+    uint8_t m_old = 0;
+    if (kMode == kEmFused) {
+        const double2 first = F.part[min((int)threadIdx.x, F.nb - 1)];
+        const int ic = min(i, n - 1);
+        e2_own = F.e2[ic];
+        m_old = F.mask[ic];
+        load_chunk(0, min(kMChunk, n));
+        const int stop = __atomic_load_n(&st->stop_at, __ATOMIC_RELAXED);
+        if (em_stopped(stop, 2 * F.it)) return;
+        if (post) run = partial_run(F.part, F.nb, first);
+    } else if (kMode == kEmSingle) {
+        load_chunk(0, min(kMChunk, n));
+        const int status = st->status, done = st->done;
+        if (status < 0 || (!final_pass && done)) return;
+    }
+    if (post) {
+        double sigma2;
+        if (!post_coef(combine_partials(run), n, F.pp, &sigma2, &pc)) {
+            if (block == 0 && threadIdx.x == 0) {
+                st->status = EMDQ_ENOINLIERS;
+                st->done = 1;
+                st->stop_at = 2 * F.it;
+            }
+            return;
+        }
+        if (block == 0 && threadIdx.x == 0) {
+            st->sigma2 = (float)sigma2;
+            st->gamma = (float)pc.gamma;
+        }
+        int changed = 0;
+        if (active && lane == 0) {
+            const float pn = post_p(e2_own, pc);
+            const uint8_t m = pn > F.pp.p_thresh ? 1 : 0;
+            changed = m != m_old;
+            F.p_out[i] = pn;
+            F.mask[i] = m;
+        }
+        changed = __syncthreads_or(changed);
+        if (threadIdx.x == 0) F.chg[block] = changed;
+    }
+    auto post_of = [&](int j) { return post ? post_p(F.e2[j], pc) : p[j]; };
+    const bool resident = n <= kMChunk;   // one staging serves both passes
+    bool preloaded = kMode != kEmBatch;   // the first chunk's registers are loaded already
+    auto stage = [&](int c0, int cn) {
+        if (preloaded) preloaded = false;
+        else load_chunk(c0, cn);
+        store_chunk(cn);
+    };
 
     float S = 0.f, Ax = 0.f, Ay = 0.f, Bx = 0.f, By = 0.f;
     for (int c0 = 0; c0 < n; c0 += kMChunk) {
@@ -304,13 +524,15 @@ __device__ __forceinline__ void mstep_body(
         stage(c0, cn);
         if (active) {
             auto acc1 = [&](const float4 &v, float pj) {
+#pragma clang fp contract(off)
                 const float dxx = v.x - me.x, dxy = v.y - me.y;   // x_j - x_i
-                const float w = fast_exp2(nal2 * (dxx * dxx + dxy * dxy)) * pj;
+                const float w =
+                    fast_exp2(nal2 * __builtin_fmaf(dxx, dxx, dxy * dxy)) * pj;
                 S += w;
-                Ax += w * dxx;
-                Ay += w * dxy;
-                Bx += w * (v.z - me.z);                          // y_j - y_i
-                By += w * (v.w - me.w);
+                Ax = __builtin_fmaf(w, dxx, Ax);
+                Ay = __builtin_fmaf(w, dxy, Ay);
+                Bx = __builtin_fmaf(w, v.z - me.z, Bx);           // y_j - y_i
+                By = __builtin_fmaf(w, v.w - me.w, By);
             };
             int t = lane;
             for (; t + 3 * kWave < cn; t += 4 * kWave) {   // 4 LDS reads in flight
@@ -345,14 +567,16 @@ __device__ __forceinline__ void mstep_body(
         if (!resident) stage(c0, cn);
         if (active && have_w) {
             auto acc2 = [&](const float4 &v, float pj) {
+#pragma clang fp contract(off)
                 const float dxx = v.x - me.x, dxy = v.y - me.y;
-                const float w = fast_exp2(nal2 * (dxx * dxx + dxy * dxy)) * pj;
+                const float w =
+                    fast_exp2(nal2 * __builtin_fmaf(dxx, dxx, dxy * dxy)) * pj;
                 const float ax = v.x - cxx, ay = v.y - cxy;    // x_j - xbar
                 const float bx = v.z - cyx, by = v.w - cyy;    // y_j - ybar
-                vx += w * (ax * ax + ay * ay);
-                vy += w * (bx * bx + by * by);
-                a += w * (bx * ax + by * ay);                  // C00 + C11
-                b += w * (by * ax - bx * ay);                  // C10 - C01
+                vx = __builtin_fmaf(w, __builtin_fmaf(ax, ax, ay * ay), vx);
+                vy = __builtin_fmaf(w, __builtin_fmaf(bx, bx, by * by), vy);
+                a = __builtin_fmaf(w, __builtin_fmaf(bx, ax, by * ay), a);      // C00 + C11
+                b = __builtin_fmaf(w, __builtin_fmaf(by, ax, -(bx * ay)), b);   // C10 - C01
             };
             int t = lane;
             for (; t + 3 * kWave < cn; t += 4 * kWave) {
@@ -380,9 +604,9 @@ __device__ __forceinline__ void mstep_body(
     // fit in FP64
     const bool need_f64 = !have_w || !(vx > 1e-2f * S) || !(vy > 1e-2f * S);
     if (need_f64) {
-        fit_row_f64(i, xy, p, n, alpha, lane, &scale, &q);
+        fit_row_f64(i, xy, post_of, n, alpha, lane, &scale, &q);
     } else {
-        const float r = sqrtf(a * a + b * b);
+        const float r = sqrtf(__builtin_fmaf(a, a, b * b));
         float ct = 1.f, stt = 0.f, ch = 1.f, sh = 0.f;
         if (r > 0.f) {
             ct = a / r;
@@ -390,15 +614,15 @@ __device__ __forceinline__ void mstep_body(
             float hx, hy;
             if (a >= 0.f) { hx = r + a; hy = b; }
             else { const float sg = b < 0.f ? -1.f : 1.f; hx = sg * b; hy = sg * (r - a); }
-            const float hn = sqrtf(hx * hx + hy * hy);
+            const float hn = sqrtf(__builtin_fmaf(hx, hx, hy * hy));
             ch = hx / hn;
             sh = hy / hn;
         }
         scale = sqrtf(vy / vx);
         const float cx = me.x + mx, cy = me.y + my;     // weighted centroid of x
         const float gx = me.z + nx, gy = me.w + ny;     // weighted centroid of y
-        const float tx = gx / scale - (ct * cx - stt * cy);
-        const float ty = gy / scale - (stt * cx + ct * cy);
+        const float tx = gx / scale - __builtin_fmaf(ct, cx, -(stt * cy));
+        const float ty = gy / scale - __builtin_fmaf(stt, cx, ct * cy);
         q = dq_make(ch, sh, tx, ty);
     }
     if (lane == 0) {
@@ -408,58 +632,139 @@ __device__ __forceinline__ void mstep_body(
 }
 
 __global__ __launch_bounds__(kEmThreads) void k_mstep(
-    const float4 *__restrict__ xy, const float *__restrict__ p, int n, float nal2,
-    double alpha, float4 *__restrict__ q_out, float *__restrict__ s_out,
-    const DevState *__restrict__ st, int final_pass) {
-    mstep_body(xy, p, n, nal2, alpha, q_out, s_out, st, final_pass, blockIdx.x);
+    const float4 *__restrict__ xy, const float *p, int n, float nal2, double alpha,
+    float4 *__restrict__ q_out, float *__restrict__ s_out, DevState *st, EmFused F) {
+    mstep_body<kEmFused>(xy, p, n, nal2, alpha, q_out, s_out, st, 0, F, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kEmThreads) void k_mstep_s(
+    const float4 *__restrict__ xy, const float *p, int n, float nal2, double alpha,
+    float4 *__restrict__ q_out, float *__restrict__ s_out, DevState *st, int final_pass) {
+    mstep_body<kEmSingle>(xy, p, n, nal2, alpha, q_out, s_out, st, final_pass, EmFused{},
+                          blockIdx.x);
 }
 
 // --------------------------------------------------------------- E-step ----
 
+// The stop decision of a single-pair fit, taken by the E-step of iteration
+// it for iteration it - 1 from the M-step's per-workgroup flags.
+struct EmStop {
+    const int *chg;         // per M-step workgroup: a mask bit changed
+    DevState *host_copy;    // pinned host memory or null: the state as the launch leaves it
+    int max_iter;
+    int it;                 // this iteration (from 1)
+};
+
 // Blend of all fits at match i with weights exp(-alpha d^2) p_j (Eqs. (2)-(3)),
 // normalisation, prediction y_hat = s (R x_i + t) (Eq. (1)), residual e_i^2.
+// The workgroup also leaves (sum p_i, sum p_i e_i^2) over its rows, in row
+// order, in part[block].  kEmFused: first the stop rule (EmStop).
+template <int kMode>
 __device__ __forceinline__ void estep_body(
     const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
     const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
-    const DevState *__restrict__ st, int block) {
+    double2 *__restrict__ part, int nb, DevState *st, const EmStop &stp, int block) {
+#pragma clang fp contract(off)
     __shared__ float4 s_xy[kEChunk];
     __shared__ float4 s_q[kEChunk];
     __shared__ float2 s_ps[kEChunk];   // (p_j, s_j - 1)
-    if (st->status < 0 || st->done) return;
+    __shared__ double2 s_part[kRowsPerBlock];
+    if (kMode == kEmBatch && (st->status < 0 || st->done)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int i = block * kRowsPerBlock + (threadIdx.x >> 6);
     const bool active = i < n;
+    // staging: a chunk's loads into registers, then LDS
+    constexpr int kPer = kEChunk / kEmThreads;
+    float4 v[kPer], qv[kPer];
+    float pv[kPer], sv[kPer];
+    auto load_chunk = [&](int c0, int cn) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int t = threadIdx.x + k * kEmThreads;
+            if (t < cn) {
+                v[k] = xy[c0 + t];
+                qv[k] = q[c0 + t];
+                pv[k] = p[c0 + t];
+                sv[k] = s[c0 + t];
+            } else {
+                v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                qv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                pv[k] = 0.f;
+                sv[k] = 0.f;
+            }
+        }
+    };
+    auto store_chunk = [&](int cn) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int t = threadIdx.x + k * kEmThreads;
+            if (t < cn) { s_xy[t] = v[k]; s_q[t] = qv[k]; s_ps[t] = make_float2(pv[k], sv[k] - 1.f); }
+        }
+        __syncthreads();
+    };
     const float4 me = active ? xy[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float p_own = p[min(i, n - 1)];   // unconditional, in bounds; used if active
+    if (kMode == kEmSingle) {
+        // the first chunk's loads are issued before the stop flag's
+        load_chunk(0, min(kEChunk, n));
+        const int status = st->status, done = st->done;
+        if (status < 0 || done) return;
+    } else if (kMode == kEmFused) {
+        // every load of the first chunk and of the stop rule is issued before
+        // the stop flag is waited on (all in bounds)
+        // chg[min(t, nb - 1)] is one of the flags, so OR-ing it is harmless;
+        // loaded unconditionally (unused when it = 1), the stop flag last
+        const int chg0 = stp.chg[min((int)threadIdx.x, nb - 1)];
+        load_chunk(0, min(kEChunk, n));
+        const int stop = __atomic_load_n(&st->stop_at, __ATOMIC_RELAXED);
+        int any = stp.it >= 2 ? chg0 : 0;
+        const bool lead = block == 0 && threadIdx.x == 0;
+        auto publish = [&]() {
+            if (lead && stp.host_copy) *stp.host_copy = *st;
+        };
+        if (em_stopped(stop, 2 * stp.it + 1)) {
+            publish();
+            return;
+        }
+        if (stp.it >= 2) {   // the M-step before formed the posteriors of it - 1
+            for (int b = threadIdx.x + kEmThreads; b < nb; b += kEmThreads) any |= stp.chg[b];
+            any = __syncthreads_or(any);
+            const int rule = stop_rule(stp.it - 1, any, stp.max_iter);
+            if (lead) {
+                st->iter = stp.it - 1;
+                st->changed = any;
+                if (rule) {
+                    st->done = 1;
+                    if (rule == 2) st->status = EMDQ_WARN_NOT_CONVERGED;
+                    st->stop_at = 2 * stp.it + 1;
+                }
+            }
+            if (rule) {
+                publish();
+                return;
+            }
+        }
+        publish();   // nothing below changes the state
+    }
+    bool preloaded = kMode != kEmBatch;   // the first chunk's registers are loaded already
     float W = 0.f, Gd = 0.f, Cd = 0.f, Sn = 0.f, X = 0.f, Y = 0.f;
     for (int c0 = 0; c0 < n; c0 += kEChunk) {
         const int cn = min(kEChunk, n - c0);
-        {
-            constexpr int kPer = kEChunk / kEmThreads;
-            float4 v[kPer], qv[kPer];
-            float pv[kPer], sv[kPer];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int t = threadIdx.x + k * kEmThreads;
-                if (t < cn) { v[k] = xy[c0 + t]; qv[k] = q[c0 + t]; pv[k] = p[c0 + t]; sv[k] = s[c0 + t]; }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int t = threadIdx.x + k * kEmThreads;
-                if (t < cn) { s_xy[t] = v[k]; s_q[t] = qv[k]; s_ps[t] = make_float2(pv[k], sv[k] - 1.f); }
-            }
-            __syncthreads();
-        }
+        if (preloaded) preloaded = false;
+        else load_chunk(c0, cn);
+        store_chunk(cn);
         if (active) {
             auto acc1 = [&](const float4 &v, const float2 &ps, const float4 &qj) {
+#pragma clang fp contract(off)
                 const float dx = v.x - me.x, dy = v.y - me.y;
-                const float w = fast_exp2(nal2 * (dx * dx + dy * dy)) * ps.x;
+                const float w = fast_exp2(nal2 * __builtin_fmaf(dx, dx, dy * dy)) * ps.x;
                 W += w;
-                Gd += w * ps.y;
-                Cd += w * (qj.x - 1.f);
-                Sn += w * qj.y;
-                X += w * qj.z;
-                Y += w * qj.w;
+                Gd = __builtin_fmaf(w, ps.y, Gd);
+                Cd = __builtin_fmaf(w, qj.x - 1.f, Cd);
+                Sn = __builtin_fmaf(w, qj.y, Sn);
+                X = __builtin_fmaf(w, qj.z, X);
+                Y = __builtin_fmaf(w, qj.w, Y);
             };
             int t = lane;
             for (; t + 3 * kWave < cn; t += 4 * kWave) {   // 4 LDS reads in flight
@@ -477,6 +782,7 @@ __device__ __forceinline__ void estep_body(
             for (; t < cn; t += kWave) acc1(s_xy[t], s_ps[t], s_q[t]);
         }
     }
+    double2 mine = make_double2(0.0, 0.0);
     if (active) {
         W = wave_sum(W);
         Gd = wave_sum(Gd);
@@ -489,31 +795,55 @@ __device__ __forceinline__ void estep_body(
             // e = y_i - F(x_i) = (y_i - x_i) - D(x_i)
             const float2 d = blend_displacement(W, Cd, Sn, X, Y, Gd, me.x, me.y);
             const float ex = (me.z - me.x) - d.x, ey = (me.w - me.y) - d.y;
-            err = ex * ex + ey * ey;
+            err = __builtin_fmaf(ex, ex, ey * ey);
         }
-        if (lane == 0) e2[i] = err;
+        if (lane == 0) {
+            e2[i] = err;
+            const double pr = (double)p_own;
+            mine = make_double2(pr, pr > 0.0 ? pr * (double)err : 0.0);
+        }
+    }
+    if (lane == 0) s_part[threadIdx.x / kWave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double2 r = s_part[0];
+        for (int w = 1; w < kRowsPerBlock; ++w) {
+            r.x += s_part[w].x;
+            r.y += s_part[w].y;
+        }
+        part[block] = r;
     }
 }
 
 __global__ __launch_bounds__(kEmThreads) void k_estep(
     const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
     const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
-    const DevState *__restrict__ st) {
-    estep_body(xy, p, q, s, n, nal2, e2, st, blockIdx.x);
+    double2 *__restrict__ part, DevState *st, EmStop stp) {
+    estep_body<kEmFused>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, stp, blockIdx.x);
 }
 
-// Finishes an EM iteration (one workgroup): p-weighted sums of the residuals
-// (FP64, fixed order), sigma^2 and gamma, new posteriors (FP64), the inlier
-// mask and the stop rule.  A kernel of its own, so the residuals of all
-// matches are visible without any cross-workgroup fence.
+__global__ __launch_bounds__(kEmThreads) void k_estep_s(
+    const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
+    const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
+    double2 *__restrict__ part, DevState *st) {
+    estep_body<kEmSingle>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, EmStop{}, blockIdx.x);
+}
+
+// Finishes an EM iteration of one pair (one workgroup of kPostThreads >=
+// kEmThreads threads; a batch pair, or a single pair in three launches per
+// iteration): the E-step partials summed as partial_run / combine_partials
+// do, sigma^2 and gamma, the posteriors (FP64) and mask of every match, and
+// the stop rule.  The same arithmetic as the posterior step at the start of
+// a fused M-step, so every mode gives the same bits.  host_copy (pinned host
+// memory, may be null): the state as this kernel leaves it, so the host
+// reads the stop flag without a copy.
 constexpr int kPostThreads = 1024;
 
 __device__ __forceinline__ void posterior_body(
     float *__restrict__ p, const float *__restrict__ e2, uint8_t *__restrict__ mask, int n,
-    double u, double sigma2_min, double gamma_min, double gamma_max, float p_thresh,
-    int max_iter, DevState *st, DevState *host_copy, int block) {
-    // host_copy (pinned host memory, may be null): the state as this kernel
-    // leaves it, so the host reads the stop flag without a copy
+    const double2 *__restrict__ part, int nb, const PostParams &pp, DevState *st,
+    DevState *host_copy) {
+#pragma clang fp contract(off)
     auto publish = [&]() {
         if (host_copy && threadIdx.x == 0) *host_copy = *st;
     };
@@ -521,27 +851,10 @@ __device__ __forceinline__ void posterior_body(
         publish();
         return;
     }
-    __shared__ double red_p[kPostThreads], red_pe[kPostThreads];
-    __shared__ int any_changed;
-    if (threadIdx.x == 0) any_changed = 0;
-    double sp = 0.0, spe = 0.0;
-    for (int r = threadIdx.x; r < n; r += kPostThreads) {
-        const double pr = (double)p[r];
-        sp += pr;
-        if (pr > 0.0) spe += pr * (double)e2[r];
-    }
-    red_p[threadIdx.x] = sp;
-    red_pe[threadIdx.x] = spe;
-    __syncthreads();
-    for (int off = kPostThreads / 2; off >= 1; off >>= 1) {
-        if (threadIdx.x < off) {
-            red_p[threadIdx.x] += red_p[threadIdx.x + off];
-            red_pe[threadIdx.x] += red_pe[threadIdx.x + off];
-        }
-        __syncthreads();
-    }
-    const double SP = red_p[0], SPE = red_pe[0];
-    if (!(SP > 0.0)) {
+    double sigma2;
+    PostCoef c;
+    const double2 first = part[min((int)threadIdx.x, nb - 1)];
+    if (!post_coef(combine_partials(partial_run(part, nb, first)), n, pp, &sigma2, &c)) {
         if (threadIdx.x == 0) {
             st->status = EMDQ_ENOINLIERS;
             st->done = 1;
@@ -549,61 +862,73 @@ __device__ __forceinline__ void posterior_body(
         publish();
         return;
     }
-    double sigma2 = SPE / (2.0 * SP);
-    if (!(sigma2 >= sigma2_min)) sigma2 = sigma2_min;
-    double gamma = SP / (double)n;
-    gamma = gamma < gamma_min ? gamma_min : (gamma > gamma_max ? gamma_max : gamma);
-    const double inv2s = 1.0 / (2.0 * sigma2);
-    const double norm = 1.0 / (6.283185307179586 * sigma2);
-    const double b = (1.0 - gamma) * u;
     int changed = 0;
     for (int r = threadIdx.x; r < n; r += kPostThreads) {
-        const double a = gamma * exp(-(double)e2[r] * inv2s) * norm;
-        const float pn = (float)(a / (a + b));
+        const float pn = post_p(e2[r], c);
         p[r] = pn;
-        const uint8_t m = pn > p_thresh ? 1 : 0;
+        const uint8_t m = pn > pp.p_thresh ? 1 : 0;
         changed |= (m != mask[r]);
         mask[r] = m;
     }
-    if (changed) atomicOr(&any_changed, 1);
-    __syncthreads();
+    changed = __syncthreads_or(changed);
     if (threadIdx.x == 0) {
         const int it = st->iter + 1;
         st->iter = it;
-        st->changed = any_changed;
+        st->changed = changed;
         st->sigma2 = (float)sigma2;
-        st->gamma = (float)gamma;
-        if (it >= 2 && !any_changed) {
-            st->done = 1;
-        } else if (it >= max_iter) {
-            st->done = 1;
-            st->status = EMDQ_WARN_NOT_CONVERGED;
-        }
+        st->gamma = (float)c.gamma;
+        const int rule = stop_rule(it, changed, pp.max_iter);
+        if (rule) st->done = 1;
+        if (rule == 2) st->status = EMDQ_WARN_NOT_CONVERGED;
     }
     publish();
 }
 
 __global__ __launch_bounds__(kPostThreads) void k_posterior(
     float *__restrict__ p, const float *__restrict__ e2, uint8_t *__restrict__ mask, int n,
-    double u, double sigma2_min, double gamma_min, double gamma_max, float p_thresh,
-    int max_iter, DevState *st, DevState *host_copy) {
-    posterior_body(p, e2, mask, n, u, sigma2_min, gamma_min, gamma_max, p_thresh, max_iter, st,
-                   host_copy, blockIdx.x);
+    const double2 *__restrict__ part, int nb, PostParams pp, DevState *st,
+    DevState *host_copy) {
+    posterior_body(p, e2, mask, n, part, nb, pp, st, host_copy);
 }
 
 // ------------------------------------------------------------ compaction ----
 
+// The stop rule after the last enqueued iteration of a single-pair fit, from
+// the flags of its final M-step (chg null: no EM decision pending).
+struct EmFinal {
+    const int *chg;
+    int nb, it, max_iter;
+};
+
 // Packs the inliers in index order: packed[2k] = (x, y, q_c - 1, q_s),
 // packed[2k+1] = (q_x, q_y, s - 1, 1) (deviation-coded, see
 // blend_displacement).  One workgroup; each thread owns a
-// contiguous run of matches, runs are ordered by an exclusive scan.
+// contiguous run of matches, runs are ordered by an exclusive scan.  First,
+// if the EM is still running after its last iteration, the stop rule
+// (EmFinal).
 __device__ __forceinline__ void compact_body(
     const float4 *__restrict__ xy, const float4 *__restrict__ q, const float *__restrict__ s,
     const uint8_t *__restrict__ mask, int n, float4 *__restrict__ packed,
-    float *__restrict__ xs, float *__restrict__ ys, DevState *st, int block) {
+    float *__restrict__ xs, float *__restrict__ ys, DevState *st, const EmFinal &fin,
+    int block) {
     __shared__ int scan[kCompactThreads];
     if (st->status < 0) return;
     const int t = threadIdx.x;
+    if (fin.chg && st->stop_at == 0) {
+        int any = 0;
+        for (int k = t; k < fin.nb; k += kCompactThreads) any |= fin.chg[k];
+        any = __syncthreads_or(any);   // also orders every read of st before the stores
+        if (t == 0) {
+            st->iter = fin.it;
+            st->changed = any;
+            const int rule = stop_rule(fin.it, any, fin.max_iter);
+            if (rule) {
+                st->done = 1;
+                st->stop_at = 2 * fin.it + 3;   // after the final M-step, 2 (it + 1)
+            }
+            if (rule == 2) st->status = EMDQ_WARN_NOT_CONVERGED;
+        }
+    }
     const int per = (n + kCompactThreads - 1) / kCompactThreads;
     const int b = t * per, e = min(b + per, n);
     int cnt = 0;
@@ -636,8 +961,8 @@ __device__ __forceinline__ void compact_body(
 __global__ __launch_bounds__(kCompactThreads) void k_compact(
     const float4 *__restrict__ xy, const float4 *__restrict__ q, const float *__restrict__ s,
     const uint8_t *__restrict__ mask, int n, float4 *__restrict__ packed,
-    float *__restrict__ xs, float *__restrict__ ys, DevState *st) {
-    compact_body(xy, q, s, mask, n, packed, xs, ys, st, blockIdx.x);
+    float *__restrict__ xs, float *__restrict__ ys, DevState *st, EmFinal fin) {
+    compact_body(xy, q, s, mask, n, packed, xs, ys, st, fin, blockIdx.x);
 }
 
 // ------------------------------------------------------------ field / warp ----
@@ -1801,6 +2126,7 @@ __device__ __forceinline__ void load_from_body(
     if (!finite2(a) || !finite2(b) || !__builtin_isfinite(pi)) {
         atomicMin(&st->status, (int)EMDQ_ENONFINITE);
         atomicExch(&st->done, 1);
+        atomicExch(&st->stop_at, kOrdLoad);
     }
 }
 
@@ -1967,6 +2293,7 @@ struct EmJob {
     float *p;
     uint8_t *mask;
     float *e2;
+    double2 *part;       // E-step sums per workgroup
     float4 *q;
     float *s;
     float4 *packed;
@@ -2006,26 +2333,28 @@ __global__ __launch_bounds__(kEmThreads) void k_mstep_b(const EmJob *__restrict_
                                                         int final_pass) {
     const EmJob &J = jobs[blockIdx.y];
     if ((int)blockIdx.x >= J.blocks) return;
-    mstep_body(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.st, final_pass, blockIdx.x);
+    mstep_body<kEmBatch>(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.st, final_pass,
+                         EmFused{}, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kEmThreads) void k_estep_b(const EmJob *__restrict__ jobs) {
     const EmJob &J = jobs[blockIdx.y];
     if ((int)blockIdx.x >= J.blocks) return;
-    estep_body(J.xy, J.p, J.q, J.s, J.n, J.nal2, J.e2, J.st, blockIdx.x);
+    estep_body<kEmBatch>(J.xy, J.p, J.q, J.s, J.n, J.nal2, J.e2, J.part, J.blocks, J.st,
+                         EmStop{}, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kPostThreads) void k_posterior_b(
     const EmJob *__restrict__ jobs, double sigma2_min, double gamma_min, double gamma_max,
     float p_thresh, int max_iter) {
     const EmJob &J = jobs[blockIdx.x];
-    posterior_body(J.p, J.e2, J.mask, J.n, J.u, sigma2_min, gamma_min, gamma_max, p_thresh,
-                   max_iter, J.st, nullptr, 0);
+    const PostParams pp{J.u, sigma2_min, gamma_min, gamma_max, p_thresh, max_iter};
+    posterior_body(J.p, J.e2, J.mask, J.n, J.part, J.blocks, pp, J.st, nullptr);
 }
 
 __global__ __launch_bounds__(kCompactThreads) void k_compact_b(const EmJob *__restrict__ jobs) {
     const EmJob &J = jobs[blockIdx.x];
-    compact_body(J.xy, J.q, J.s, J.mask, J.n, J.packed, J.xs, J.ys, J.st, 0);
+    compact_body(J.xy, J.q, J.s, J.mask, J.n, J.packed, J.xs, J.ys, J.st, EmFinal{}, 0);
 }
 
 __global__ void k_gather_states(const EmJob *__restrict__ jobs, int n_pairs,
@@ -2062,6 +2391,8 @@ struct emdq_model_s {
     float *p = nullptr;
     uint8_t *mask = nullptr;
     float *e2 = nullptr;
+    double2 *part = nullptr;   // EM: E-step sums per workgroup
+    int *chg = nullptr;        // EM: per M-step workgroup, a mask bit changed
     float4 *q = nullptr;
     float *s = nullptr;
     float4 *packed = nullptr;
@@ -2224,6 +2555,9 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     ok = ok && hipMalloc((void **)&m->p, n * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->mask, n) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->e2, n * sizeof(float)) == hipSuccess;
+    const size_t nb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    ok = ok && hipMalloc((void **)&m->part, nb * sizeof(double2)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&m->chg, nb * sizeof(int)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->q, n * sizeof(float4)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->s, n * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->packed, 2 * n * sizeof(float4)) == hipSuccess;
@@ -2232,7 +2566,7 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     ok = ok && hipMalloc((void **)&m->st, sizeof(DevState)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&m->host_st, sizeof(DevState), hipHostMallocDefault) ==
                    hipSuccess;
-    // coherent: the posterior kernel stores the stop flags straight into them
+    // coherent: the E-step kernel stores the stop flags straight into them
     ok = ok && hipHostMalloc((void **)&m->em_st, 2 * sizeof(DevState), hipHostMallocCoherent) ==
                    hipSuccess;
     ok = ok && hipHostGetDevicePointer((void **)&m->em_st_dev, m->em_st, 0) == hipSuccess;
@@ -2259,6 +2593,8 @@ void emdq_model_free(emdq_model m) {
     (void)hipFree(m->p);
     (void)hipFree(m->mask);
     (void)hipFree(m->e2);
+    (void)hipFree(m->part);
+    (void)hipFree(m->chg);
     (void)hipFree(m->q);
     (void)hipFree(m->s);
     (void)hipFree(m->packed);
@@ -2310,28 +2646,48 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
                            (const float2 *)src_xy, (const float2 *)dst_xy, n, m->xy, m->p,
                            m->mask, m->st);
     if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
-    auto mstep = [&](int final_pass) {
-        hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy, m->p,
-                           n, nal2, alpha, m->q, m->s, m->st, final_pass);
+    const PostParams pp{u, (double)prm.sigma2_min, (double)prm.gamma_min, (double)prm.gamma_max,
+                        prm.p_thresh, prm.max_iter};
+    // Up to kFusedMaxN matches the posterior step runs inside the M-step (two
+    // launches per iteration; every M-step workgroup forms all n posteriors
+    // in FP64); above it in its own one-workgroup kernel (three launches).
+    const bool fused = n <= kFusedMaxN;
+    // M-step of iteration it (from 1); fused: the posteriors of iteration
+    // it - 1 first, when it >= 2
+    auto mstep = [&](int it, int final_pass) {
+        if (fused) {
+            const EmFused F{m->e2, m->part, m->p, m->mask, m->chg, pp, (int)em_blocks, it};
+            hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
+                               m->p, n, nal2, alpha, m->q, m->s, m->st, F);
+        } else {
+            hipLaunchKernelGGL(k_mstep_s, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
+                               m->p, n, nal2, alpha, m->q, m->s, m->st, final_pass);
+        }
     };
     // EM: iterations are enqueued in chunks; every kernel returns at once
-    // after the device-side stop flag is set, so a chunk may overshoot.  The
-    // stop flag after chunk k is read while chunk k + 1 already runs, so the
-    // GPU does not wait for the host between chunks.
+    // once the EM has stopped, so a chunk may overshoot.  The stop flag after
+    // chunk k is read while chunk k + 1 already runs, so the GPU does not
+    // wait for the host between chunks.
     int enqueued = 0;
     for (int k = 0;; ++k) {
-        // the chunk's last posterior also stores the state into host slot
-        // k & 1 (a chunk holds at least one iteration: the loop leaves once
-        // max_iter iterations are enqueued)
+        // the chunk's last E-step (fused) or posterior kernel also stores the
+        // state into host slot k & 1 (a chunk holds at least one iteration:
+        // the loop leaves once max_iter iterations are enqueued)
         for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
             const bool last = c + 1 == kEmChunk || enqueued + 1 == prm.max_iter;
-            mstep(0);
-            hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
-                               m->p, m->q, m->s, n, nal2, m->e2, m->st);
-            hipLaunchKernelGGL(k_posterior, dim3(1), dim3(kPostThreads), 0, stream, m->p, m->e2,
-                               m->mask, n, u, (double)prm.sigma2_min, (double)prm.gamma_min,
-                               (double)prm.gamma_max, prm.p_thresh, prm.max_iter, m->st,
-                               last ? &m->em_st_dev[k & 1] : nullptr);
+            DevState *slot = last ? &m->em_st_dev[k & 1] : nullptr;
+            const int it = enqueued + 1;
+            mstep(it, 0);
+            if (fused) {
+                const EmStop X{m->chg, slot, prm.max_iter, it};
+                hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
+                                   m->p, m->q, m->s, n, nal2, m->e2, m->part, m->st, X);
+            } else {
+                hipLaunchKernelGGL(k_estep_s, dim3(em_blocks), dim3(kEmThreads), 0, stream,
+                                   m->xy, m->p, m->q, m->s, n, nal2, m->e2, m->part, m->st);
+                hipLaunchKernelGGL(k_posterior, dim3(1), dim3(kPostThreads), 0, stream, m->p,
+                                   m->e2, m->mask, n, m->part, (int)em_blocks, pp, m->st, slot);
+            }
         }
         if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
         EMDQ_HIP(hipEventRecord(m->em_ev[k & 1], stream));
@@ -2342,10 +2698,14 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
         }
         if (enqueued >= prm.max_iter) break;
     }
-    // final fit with the final posteriors, then pack the inliers
-    mstep(1);
+    // the fit with the final posteriors (fused: the posteriors of the last
+    // enqueued iteration first; nothing if the EM stopped earlier, as that
+    // M-step fitted already), then (fused) the last stop decision and the
+    // inliers packed
+    mstep(enqueued + 1, 1);
+    const EmFinal fin{fused ? m->chg : nullptr, (int)em_blocks, enqueued, prm.max_iter};
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, stream, m->xy, m->q,
-                       m->s, m->mask, n, m->packed, m->xs, m->ys, m->st);
+                       m->s, m->mask, n, m->packed, m->xs, m->ys, m->st, fin);
     return check_launch();
 }
 
@@ -2384,7 +2744,7 @@ emdq_status emdq_model_set_nodes(emdq_model m, const float *x_xy, const float *s
     if (rc == EMDQ_OK) {
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, m->st);
         hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, stream, m->xy, m->q,
-                           m->s, m->mask, n, m->packed, m->xs, m->ys, m->st);
+                           m->s, m->mask, n, m->packed, m->xs, m->ys, m->st, EmFinal{});
         rc = check_launch();
     }
     // the staging buffers are released only after the copies completed
@@ -2831,6 +3191,7 @@ emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
         J.p = m->p;
         J.mask = m->mask;
         J.e2 = m->e2;
+        J.part = m->part;
         J.q = m->q;
         J.s = m->s;
         J.packed = m->packed;

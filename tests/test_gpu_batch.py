@@ -50,6 +50,40 @@ def test_batch_fit_and_field_bit_identical_to_single_calls():
         assert torch.equal(outs_b[i], outs_s[i]), i
 
 
+@pytest.mark.parametrize("max_iter", [1, 2, 3, 100])
+def test_stop_rule_both_single_pair_paths(max_iter):
+    """Single-pair fits take two launches per iteration (posterior step in
+    the M-step, stop rule in the E-step) up to 2048 matches and three above.
+    For a 1504-match and a 2807-match pair, under an iteration cap or none:
+    status, iterations and mask equal the oracle's, and every result equals
+    the batched fit's bits (whose posterior is a kernel of its own)."""
+    torch = torch_or_skip()
+    E = emdq()
+    pairs = synth.gen_batch(2, seed=3007, with_frame=False)
+    assert [p.cfg.n_matches for p in pairs] == [1504, 2807]
+    prm = E.emdq_params_default()
+    prm.max_iter = max_iter
+    srcs = [to_dev(p.src, torch) for p in pairs]
+    dsts = [to_dev(p.dst, torch) for p in pairs]
+    sizes = [(p.cfg.width, p.cfg.height) for p in pairs]
+    mb = [E.Model(p.cfg.n_matches) for p in pairs]
+    b = E.Batch(2)
+    b.fit(mb, srcs, dsts, sizes, params=prm)
+    for i, p in enumerate(pairs):
+        ref = O.fit(p.src, p.dst, p.cfg.width, p.cfg.height, O.params(max_iter=max_iter))
+        m = E.Model(p.cfg.n_matches)
+        m.fit(srcs[i], dsts[i], p.cfg.width, p.cfg.height, prm)
+        r, rb = m.results(), mb[i].results()
+        print(f"pair {i} n {p.cfg.n_matches} max_iter {max_iter}: status {r['status']} "
+              f"iters {r['iters']} (oracle {ref.status}, {ref.iters})", flush=True)
+        assert r["status"] == ref.status and r["iters"] == ref.iters
+        assert np.array_equal(r["mask"], ref.mask)
+        for key in ("status", "iters", "n_in", "sigma2", "gamma"):
+            assert r[key] == rb[key], (i, key)
+        for key in ("p", "q", "scale", "mask"):
+            assert np.array_equal(r[key], rb[key]), (i, key)
+
+
 def test_batch_against_oracle():
     """Masks, iterations and the sampled field of every pair of a mixed
     batch against the oracle."""
