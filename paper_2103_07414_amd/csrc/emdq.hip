@@ -226,16 +226,33 @@ struct PostParams {
 
 // p = a / (a + b), a = gamma exp(-e^2 / (2 sigma^2)) / (2 pi sigma^2),
 // b = (1 - gamma) u (FP64)
+// and, in FP32, p = 1 / (1 + 2^(e^2 s + l)) with s = log2(e) / (2 sigma^2),
+// l = log2(b (2 pi sigma^2) / gamma); th = p_thresh
 struct PostCoef {
     double gamma, inv2s, norm, b;
+    float s, l, th;
 };
+
+// Half-width of the band around p_thresh in which the FP32 posterior is
+// replaced by the FP64 one.  The FP32 form is off by less than 1e-5 (the
+// exponent's rounding over |e^2 s| <= 150 and the 1-ulp exp2), so outside
+// the band both forms fall on the same side of the threshold.
+constexpr float kPostBand = 1e-3f;
 
 // Every FP64 operation of the posterior step is rounded on its own
 // (contraction off), so the kernels that inline it agree bit for bit.
-__device__ __forceinline__ float post_p(float e2, const PostCoef &c) {
+__device__ __forceinline__ float post_p64(float e2, const PostCoef &c) {
 #pragma clang fp contract(off)
     const double a = c.gamma * exp(-(double)e2 * c.inv2s) * c.norm;
     return (float)(a / (a + c.b));
+}
+
+// The posterior of a match: the FP32 form, or the FP64 one inside the band
+// around p_thresh, so that the inlier mask is always decided as in FP64.
+__device__ __forceinline__ float post_p(float e2, const PostCoef &c) {
+#pragma clang fp contract(off)
+    const float p = 1.f / (1.f + fast_exp2(__builtin_fmaf(e2, c.s, c.l)));
+    return fabsf(p - c.th) > kPostBand ? p : post_p64(e2, c);
 }
 
 // Fixed-order sum of the E-step partials part[0, nb): thread t < kEmThreads
@@ -289,6 +306,9 @@ __device__ __forceinline__ bool post_coef(double2 S, int n, const PostParams &pp
     c->inv2s = 1.0 / (2.0 * sigma2);
     c->norm = 1.0 / (6.283185307179586 * sigma2);
     c->b = (1.0 - gamma) * pp.u;
+    c->s = (float)(c->inv2s * 1.4426950408889634);
+    c->l = (float)log2(c->b / (c->gamma * c->norm));
+    c->th = pp.p_thresh;
     *sigma2_out = sigma2;
     return true;
 }
@@ -518,19 +538,30 @@ __device__ __forceinline__ void mstep_body(
         store_chunk(cn);
     };
 
+    // Fused mode (n <= kMChunk, so the matches are staged once): the first
+    // pass keeps every weight in LDS and the second reads it back instead of
+    // recomputing it (the same float either way).
+    constexpr bool kKeepW = kMode == kEmFused;
+    static_assert(!kKeepW || kFusedMaxN <= kMChunk, "fused M-step stages all matches once");
+    __shared__ float s_w[kKeepW ? kRowsPerBlock * kMChunk : 1];
+    float *const wrow = s_w + (kKeepW ? (threadIdx.x >> 6) * kMChunk : 0);
+    auto weight = [&](const float4 &v, float pj) {
+#pragma clang fp contract(off)
+        const float dxx = v.x - me.x, dxy = v.y - me.y;   // x_j - x_i
+        return fast_exp2(nal2 * __builtin_fmaf(dxx, dxx, dxy * dxy)) * pj;
+    };
     float S = 0.f, Ax = 0.f, Ay = 0.f, Bx = 0.f, By = 0.f;
     for (int c0 = 0; c0 < n; c0 += kMChunk) {
         const int cn = min(kMChunk, n - c0);
         stage(c0, cn);
         if (active) {
-            auto acc1 = [&](const float4 &v, float pj) {
+            auto acc1 = [&](const float4 &v, float pj, int t) {
 #pragma clang fp contract(off)
-                const float dxx = v.x - me.x, dxy = v.y - me.y;   // x_j - x_i
-                const float w =
-                    fast_exp2(nal2 * __builtin_fmaf(dxx, dxx, dxy * dxy)) * pj;
+                const float w = weight(v, pj);
+                if (kKeepW) wrow[t] = w;
                 S += w;
-                Ax = __builtin_fmaf(w, dxx, Ax);
-                Ay = __builtin_fmaf(w, dxy, Ay);
+                Ax = __builtin_fmaf(w, v.x - me.x, Ax);
+                Ay = __builtin_fmaf(w, v.y - me.y, Ay);
                 Bx = __builtin_fmaf(w, v.z - me.z, Bx);           // y_j - y_i
                 By = __builtin_fmaf(w, v.w - me.w, By);
             };
@@ -540,12 +571,12 @@ __device__ __forceinline__ void mstep_body(
                              v3 = s_xy[t + 3 * kWave];
                 const float p0 = s_p[t], p1 = s_p[t + kWave], p2 = s_p[t + 2 * kWave],
                             p3 = s_p[t + 3 * kWave];
-                acc1(v0, p0);
-                acc1(v1, p1);
-                acc1(v2, p2);
-                acc1(v3, p3);
+                acc1(v0, p0, t);
+                acc1(v1, p1, t + kWave);
+                acc1(v2, p2, t + 2 * kWave);
+                acc1(v3, p3, t + 3 * kWave);
             }
-            for (; t < cn; t += kWave) acc1(s_xy[t], s_p[t]);
+            for (; t < cn; t += kWave) acc1(s_xy[t], s_p[t], t);
         }
     }
     S = wave_sum(S);
@@ -566,11 +597,9 @@ __device__ __forceinline__ void mstep_body(
         const int cn = min(kMChunk, n - c0);
         if (!resident) stage(c0, cn);
         if (active && have_w) {
-            auto acc2 = [&](const float4 &v, float pj) {
+            auto acc2 = [&](const float4 &v, float pj, int t) {
 #pragma clang fp contract(off)
-                const float dxx = v.x - me.x, dxy = v.y - me.y;
-                const float w =
-                    fast_exp2(nal2 * __builtin_fmaf(dxx, dxx, dxy * dxy)) * pj;
+                const float w = kKeepW ? wrow[t] : weight(v, pj);
                 const float ax = v.x - cxx, ay = v.y - cxy;    // x_j - xbar
                 const float bx = v.z - cyx, by = v.w - cyy;    // y_j - ybar
                 vx = __builtin_fmaf(w, __builtin_fmaf(ax, ax, ay * ay), vx);
@@ -582,14 +611,15 @@ __device__ __forceinline__ void mstep_body(
             for (; t + 3 * kWave < cn; t += 4 * kWave) {
                 const float4 v0 = s_xy[t], v1 = s_xy[t + kWave], v2 = s_xy[t + 2 * kWave],
                              v3 = s_xy[t + 3 * kWave];
-                const float p0 = s_p[t], p1 = s_p[t + kWave], p2 = s_p[t + 2 * kWave],
-                            p3 = s_p[t + 3 * kWave];
-                acc2(v0, p0);
-                acc2(v1, p1);
-                acc2(v2, p2);
-                acc2(v3, p3);
+                const float p0 = kKeepW ? 0.f : s_p[t], p1 = kKeepW ? 0.f : s_p[t + kWave],
+                            p2 = kKeepW ? 0.f : s_p[t + 2 * kWave],
+                            p3 = kKeepW ? 0.f : s_p[t + 3 * kWave];
+                acc2(v0, p0, t);
+                acc2(v1, p1, t + kWave);
+                acc2(v2, p2, t + 2 * kWave);
+                acc2(v3, p3, t + 3 * kWave);
             }
-            for (; t < cn; t += kWave) acc2(s_xy[t], s_p[t]);
+            for (; t < cn; t += kWave) acc2(s_xy[t], kKeepW ? 0.f : s_p[t], t);
         }
     }
     if (!active) return;
