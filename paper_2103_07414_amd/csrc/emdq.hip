@@ -42,6 +42,7 @@ namespace {
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kWave = 64;
 constexpr int kRowsPerBlock = 8;        // EM kernels: one wavefront per match
+template <int V> struct IntTag { static constexpr int value = V; };
 constexpr int kEmThreads = kWave * kRowsPerBlock;
 #ifndef EMDQ_MCHUNK
 #define EMDQ_MCHUNK 2048
@@ -1220,86 +1221,108 @@ __device__ __forceinline__ void field_body(
         }
     }
 
-    // ---- split-K reduction: wavefront ks keeps registers [ks*R, ks*R + R)
-    // of every row block
-    const int rbase = ks * kRegsOwned;
-    if constexpr (SPLITK > 1) {
-        // two passes of three components each, so the partials need half
-        // the LDS
+    // ---- split-K reduction, then the epilogue, specialised per wavefront of
+    // the tile: wavefront KS keeps registers [KS*R, KS*R + R) of every row
+    // block.  ks is wavefront-uniform, so the switch below is a scalar
+    // branch; with KS a compile-time constant those registers are fixed (a
+    // runtime register index compiles to compare / select chains over all
+    // 16 accumulator registers, thousands of VALU instructions that cannot
+    // overlap the MFMA pipe).
+    auto finish = [&](auto ks_tag) {
+        constexpr int KS = decltype(ks_tag)::value;
+        constexpr int rbase = KS * kRegsOwned;
+        if constexpr (SPLITK > 1) {
+            // two passes of three components each, so the partials need half
+            // the LDS
 #pragma unroll
-        for (int c0 = 0; c0 < 6; c0 += 3) {
-            if (c0 > 0) __syncthreads();   // the first pass's reads are done
-            int slot = 0;
+            for (int c0 = 0; c0 < 6; c0 += 3) {
+                if (c0 > 0) __syncthreads();   // the first pass's reads are done
+                int slot = 0;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                if (r >= rbase && r < rbase + kRegsOwned) continue;
+                for (int r = 0; r < 16; ++r) {
+                    if (r >= rbase && r < rbase + kRegsOwned) continue;
 #pragma unroll
-                for (int bl = 0; bl < RB; ++bl)
+                    for (int bl = 0; bl < RB; ++bl)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        lds.part[wave][(slot * RB + bl) * 3 + c][lane] = acc[bl][c0 + c][r];
-                ++slot;
-            }
-            __syncthreads();
-            // add the partials in wavefront order 0, 1, ..., SPLITK-1
-            const int wbase = (wave / SPLITK) * SPLITK;
+                        for (int c = 0; c < 3; ++c)
+                            lds.part[wave][(slot * RB + bl) * 3 + c][lane] = acc[bl][c0 + c][r];
+                    ++slot;
+                }
+                __syncthreads();
+                // add the partials in wavefront order 0, 1, ..., SPLITK-1
+                const int wbase = (wave / SPLITK) * SPLITK;
 #pragma unroll
-            for (int rr = 0; rr < kRegsOwned; ++rr) {
-                const int r = rbase + rr;
+                for (int rr = 0; rr < kRegsOwned; ++rr) {
+                    const int r = rbase + rr;
 #pragma unroll
-                for (int bl = 0; bl < RB; ++bl)
+                    for (int bl = 0; bl < RB; ++bl)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        float sum = 0.f;
-                        for (int src = 0; src < SPLITK; ++src) {
-                            float v;
-                            if (src == ks) {
-                                v = acc[bl][c0 + c][r];
-                            } else {
-                                // slot of register r in wavefront src's list
-                                const int src_base = src * kRegsOwned;
-                                const int sl = r < src_base ? r : r - kRegsOwned;
-                                v = lds.part[wbase + src][(sl * RB + bl) * 3 + c][lane];
+                        for (int c = 0; c < 3; ++c) {
+                            float sum = 0.f;
+                            for (int src = 0; src < SPLITK; ++src) {
+                                float v;
+                                if (src == KS) {
+                                    v = acc[bl][c0 + c][r];
+                                } else {
+                                    // slot of register r in wavefront src's list
+                                    const int src_base = src * kRegsOwned;
+                                    const int sl = r < src_base ? r : r - kRegsOwned;
+                                    v = lds.part[wbase + src][(sl * RB + bl) * 3 + c][lane];
+                                }
+                                sum = src == 0 ? v : sum + v;
                             }
-                            sum = src == 0 ? v : sum + v;
+                            acc[bl][c0 + c][r] = sum;
                         }
-                        acc[bl][c0 + c][r] = sum;
-                    }
+                }
             }
         }
-    }
-    if (tile >= n_tiles) return;
+        if (tile >= n_tiles) return;
 
-    // ---- epilogue: DQ normalisation, Eq. (1), then (warp) sample + merge,
-    // in groups of kGroupPix pixels per lane (fewer where more accumulator
-    // registers are still live, so that nothing spills)
-    constexpr int kGroupPix = SPLITK >= 4 ? 4 : 2;
-    int pzx[kGroupPix], pzy[kGroupPix];
-    float2 pd[kGroupPix];
-    bool live[kGroupPix];
+        // ---- epilogue: DQ normalisation, Eq. (1), then (warp) sample + merge,
+        // in groups of kGroupPix pixels per lane (fewer where more accumulator
+        // registers are still live, so that nothing spills)
+        constexpr int kGroupPix = SPLITK >= 4 ? 4 : 2;
+        int pzx[kGroupPix], pzy[kGroupPix];
+        float2 pd[kGroupPix];
+        bool live[kGroupPix];
 #pragma unroll
-    for (int bl = 0; bl < RB; ++bl)
+        for (int bl = 0; bl < RB; ++bl)
 #pragma unroll
-    for (int rr = 0; rr < kRegsOwned; ++rr) {
-        const int r = rbase + rr, i = rr % kGroupPix;
-        const int zx = px0 + col;
-        const int zy = py0 + kTile * bl + 8 * (r >> 2) + 4 * half + (r & 3);
-        const float fzx = (float)zx, fzy = (float)zy;
-        pzx[i] = zx;
-        pzy[i] = zy;
-        live[i] = zx < zx0 + w && zy < zy0 + h;
-        pd[i] = blend_displacement(acc[bl][5][r], acc[bl][0][r], acc[bl][1][r], acc[bl][2][r],
-                                   acc[bl][3][r], acc[bl][4][r], fzx, fzy);
-        if constexpr (MODE == kModeField) {
-            if (live[i])
-                out[(size_t)(zy - zy0) * w + (zx - zx0)] =
-                    bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
-                        : make_float2(fzx + pd[i].x, fzy + pd[i].y);
-        } else if constexpr (!EMDQ_WARP_BATCH) {
-            if (live[i]) warp_merge(zx, zy, pd[i], frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
-        } else if (i == kGroupPix - 1) {
-            warp_merge_batch<kGroupPix>(pzx, pzy, pd, live, zx0, zy0, frame, fw, fh, fpitch,
-                                        canvas, cpitch, ox, oy);
+        for (int rr = 0; rr < kRegsOwned; ++rr) {
+            const int r = rbase + rr, i = rr % kGroupPix;
+            const int zx = px0 + col;
+            const int zy = py0 + kTile * bl + 8 * (r >> 2) + 4 * half + (r & 3);
+            const float fzx = (float)zx, fzy = (float)zy;
+            pzx[i] = zx;
+            pzy[i] = zy;
+            live[i] = zx < zx0 + w && zy < zy0 + h;
+            pd[i] = blend_displacement(acc[bl][5][r], acc[bl][0][r], acc[bl][1][r], acc[bl][2][r],
+                                       acc[bl][3][r], acc[bl][4][r], fzx, fzy);
+            if constexpr (MODE == kModeField) {
+                if (live[i])
+                    out[(size_t)(zy - zy0) * w + (zx - zx0)] =
+                        bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
+                            : make_float2(fzx + pd[i].x, fzy + pd[i].y);
+            } else if constexpr (!EMDQ_WARP_BATCH) {
+                if (live[i]) warp_merge(zx, zy, pd[i], frame, fw, fh, fpitch, canvas, cpitch, ox, oy);
+            } else if (i == kGroupPix - 1) {
+                warp_merge_batch<kGroupPix>(pzx, pzy, pd, live, zx0, zy0, frame, fw, fh, fpitch,
+                                            canvas, cpitch, ox, oy);
+            }
+        }
+    };
+    static_assert(SPLITK == 1 || SPLITK == 2 || SPLITK == 4, "split-K 1, 2 or 4");
+    if constexpr (SPLITK == 1) {
+        finish(IntTag<0>{});
+    } else if constexpr (SPLITK == 2) {
+        if (ks == 0) finish(IntTag<0>{});
+        else finish(IntTag<1>{});
+    } else {
+        switch (ks) {
+        case 0: finish(IntTag<0>{}); break;
+        case 1: finish(IntTag<1>{}); break;
+        case 2: finish(IntTag<2>{}); break;
+        default: finish(IntTag<3>{}); break;
         }
     }
 }
