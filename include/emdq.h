@@ -330,8 +330,12 @@ emdq_status emdq_batch_warp(emdq_batch b, int n_pairs, const emdq_model *models,
                             const emdq_region *regions, hipStream_t stream);
 
 /* Autotuner of the batched field / warp launch: the field kernel comes in
- * three shapes (split-K 4, 2, 1: four wavefronts on one 32 x 32 tile, two
- * tiles, or four tiles per workgroup).  Times each shape on emdq_batch_field
+ * four shapes (0, 1, 2: split-K 4, 2, 1, i.e. four wavefronts on one 32 x 32
+ * tile, two tiles, or four tiles per workgroup; 3: split-K 4 on 32 x 64
+ * tiles, two 32-row blocks per wavefront at two wavefronts per SIMD).
+ * Shapes 0 and 3 give the same bits.  Until a shape is chosen, a batch uses
+ * shape 3 when its regions hold at least 768 32 x 64 tiles, else shape 0
+ * (the rule of the single-pair FP32 launches).  Times each shape on emdq_batch_field
  * of these pairs and regions (which it therefore writes), keeps the fastest
  * for later batched calls and stores it in *variant_out (nullable).  With a
  * cache_path (nullable, host file), the choice is first looked up there by
@@ -342,7 +346,7 @@ emdq_status emdq_batch_autotune(emdq_batch b, int n_pairs, const emdq_model *mod
                                 const emdq_region *regions, const char *cache_path,
                                 int *variant_out, hipStream_t stream);
 
-/* Selects the field-kernel shape of later batched calls (0, 1, 2 as above). */
+/* Selects the field-kernel shape of later batched calls (0 to 3 as above). */
 emdq_status emdq_batch_set_variant(emdq_batch b, int variant);
 
 /* Builds the job table of a batched field (warp = 0) or warp (warp = 1)

@@ -74,6 +74,9 @@ constexpr int kRing = EMDQ_RING;       // field kernel: record ring depth (K ste
 // (3 keeps at least two wavefronts on every SIMD through the last partial
 // round of tiles; 4 spills)
 constexpr int kFieldWaves = EMDQ_FIELD_WAVES;
+// wavefronts per SIMD the FP32 field kernel's registers are held to, by row
+// blocks per wavefront (two blocks hold 192 accumulators)
+constexpr int field_waves(int rb) { return rb == 1 ? kFieldWaves : 2; }
 #ifndef EMDQ_HALF_TABLES
 #define EMDQ_HALF_TABLES 1  // half-precision blend: factor tables instead of in-loop exps
 #endif
@@ -1328,7 +1331,7 @@ __device__ __forceinline__ void field_body(
 }
 
 template <int MODE, int SPLITK, int RB>
-__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(kFieldWaves, kFieldWaves))) void k_field(
+__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(field_waves(RB), field_waves(RB)))) void k_field(
     const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
     int zy0, int w, int h, int tiles_x, int n_tiles, float2 *__restrict__ out,
     const uint8_t *__restrict__ frame, int fw, int fh, int fpitch, float4 *__restrict__ canvas,
@@ -2326,10 +2329,19 @@ __global__ void k_start_adam(float *__restrict__ wts, float *__restrict__ m1,
 }
 
 constexpr int kSplitK = EMDQ_SPLITK;
-#ifndef EMDQ_ROWBLOCKS
-#define EMDQ_ROWBLOCKS 1
+// FP32 field launches take two 32-row blocks per wavefront (2 wavefronts per
+// SIMD, 512 workgroups at once) from this many 32 x 64 tiles on, 1.5 such
+// rounds; smaller launches keep one row block (3 wavefronts per SIMD, 768
+// workgroups at once), whose rounds quantise them better.
+#ifndef EMDQ_RB2_MIN_TILES
+#define EMDQ_RB2_MIN_TILES 768
 #endif
-constexpr int kRowBlocks = EMDQ_ROWBLOCKS;
+constexpr long long kRb2MinTiles = EMDQ_RB2_MIN_TILES;
+
+inline long long tiles64(int w, int h) {
+    return (long long)((w + kTile - 1) / kTile) * ((h + 2 * kTile - 1) / (2 * kTile));
+}
+inline int field_row_blocks(long long n64) { return n64 >= kRb2MinTiles ? 2 : 1; }
 
 // ---------------------------------------------------------------- batches ----
 //
@@ -2416,8 +2428,8 @@ __global__ void k_gather_states(const EmJob *__restrict__ jobs, int n_pairs,
     if (i < n_pairs) out[i] = *jobs[i].st;
 }
 
-template <int MODE, int SPLITK>
-__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(kFieldWaves, kFieldWaves))) void k_field_b(const FieldJob *__restrict__ jobs,
+template <int MODE, int SPLITK, int RB>
+__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(field_waves(RB), field_waves(RB)))) void k_field_b(const FieldJob *__restrict__ jobs,
                                                            int n_jobs) {
     int lo = 0, hi = n_jobs - 1;   // last job whose first workgroup is <= blockIdx.x
     while (lo < hi) {
@@ -2425,7 +2437,7 @@ __global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(k
         if (jobs[mid].block_base <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
     }
     const FieldJob &J = jobs[lo];
-    field_body<MODE, SPLITK, kRowBlocks>(J.packed, J.st, J.nal2, J.zx0, J.zy0, J.w, J.h,
+    field_body<MODE, SPLITK, RB>(J.packed, J.st, J.nal2, J.zx0, J.zy0, J.w, J.h,
                                           J.tiles_x, J.n_tiles, J.out, J.frame, J.fw, J.fh,
                                           J.fpitch, J.canvas, J.cpitch, J.ox, J.oy,
                                           (int)blockIdx.x - J.block_base);
@@ -2492,8 +2504,9 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
 emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h, float2 *out,
                          const uint8_t *frame, int fw, int fh, int fpitch, float4 *canvas,
                          int cpitch, int ox, int oy, hipStream_t stream) {
+    const int rb = field_row_blocks(tiles64(w, h));   // FP32 path only
     const int tiles_x = (w + kTile - 1) / kTile;
-    const int tiles_y = (h + kTile * kRowBlocks - 1) / (kTile * kRowBlocks);
+    const int tiles_y = (h + kTile * rb - 1) / (kTile * rb);
     const long long n_tiles = (long long)tiles_x * tiles_y;
     constexpr int tiles_per_wg = 4 / kSplitK;
     const long long blocks = (n_tiles + tiles_per_wg - 1) / tiles_per_wg;
@@ -2543,15 +2556,18 @@ emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h,
         return check_launch();
     }
     const float nal2 = -m->alpha * kLog2e;
-    if (mode == kModeField)
-        hipLaunchKernelGGL((k_field<kModeField, kSplitK, kRowBlocks>), dim3((unsigned)blocks),
-                           dim3(kFieldThreads), 0, stream, m->packed, m->st, nal2, zx0, zy0, w,
-                           h, tiles_x, (int)n_tiles, out, nullptr, 0, 0, 0, nullptr, 0, 0, 0);
-    else
-        hipLaunchKernelGGL((k_field<kModeWarp, kSplitK, kRowBlocks>), dim3((unsigned)blocks),
-                           dim3(kFieldThreads), 0, stream, m->packed, m->st, nal2, zx0, zy0, w,
-                           h, tiles_x, (int)n_tiles, nullptr, frame, fw, fh, fpitch, canvas,
-                           cpitch, ox, oy);
+#define EMDQ_F(M, R, O, F, C)                                                                \
+    hipLaunchKernelGGL((k_field<M, kSplitK, R>), dim3((unsigned)blocks), dim3(kFieldThreads), \
+                       0, stream, m->packed, m->st, nal2, zx0, zy0, w, h, tiles_x,           \
+                       (int)n_tiles, O, F, fw, fh, fpitch, C, cpitch, ox, oy)
+    if (mode == kModeField) {
+        if (rb == 2) EMDQ_F(kModeField, 2, out, nullptr, nullptr);
+        else EMDQ_F(kModeField, 1, out, nullptr, nullptr);
+    } else {
+        if (rb == 2) EMDQ_F(kModeWarp, 2, nullptr, frame, canvas);
+        else EMDQ_F(kModeWarp, 1, nullptr, frame, canvas);
+    }
+#undef EMDQ_F
     return check_launch();
 }
 
@@ -2978,7 +2994,7 @@ struct emdq_batch_s {
     FieldJob *field_jobs = nullptr;  // device
     StartJob *start_jobs = nullptr;  // device
     FieldJob *prepared = nullptr;    // device: the table of emdq_batch_prepare
-    int variant = 0;                 // field-kernel shape (autotuner)
+    int variant = -1;                // field-kernel shape (autotuner); -1: by size
     int prep_mode = -1, prep_pairs = 0, prep_variant = 0;
     long long prep_blocks = 0;
     DevState *states = nullptr;      // device, gathered per chunk
@@ -3033,13 +3049,15 @@ emdq_status batch_region_ok(const emdq_region &r, int mode) {
 
 // Field-kernel shapes the batched launch can use (split-K 4: one 32 x 32 tile
 // per workgroup of four wavefronts; 2: two tiles; 1: four tiles).
-constexpr int kBatchVariants = 3;
-constexpr int kVariantSplitK[kBatchVariants] = {4, 2, 1};
+constexpr int kBatchVariants = 4;
+constexpr int kVariantSplitK[kBatchVariants] = {4, 2, 1, 4};
+constexpr int kVariantRows[kBatchVariants] = {1, 1, 1, 2};   // 32-row blocks per wavefront
 
 // Job table of a batched field / warp launch, the pairs ordered by match
 // count (largest first), so the most expensive tiles are dispatched first.
 emdq_status fill_field_jobs(FieldJob *jobs, int n_pairs, const emdq_model *models,
-                            const emdq_region *regions, int splitk, long long *blocks_out) {
+                            const emdq_region *regions, int splitk, int rows,
+                            long long *blocks_out) {
     int *order = (int *)malloc(sizeof(int) * (size_t)n_pairs);
     if (!order) return EMDQ_ENOMEM;
     for (int i = 0; i < n_pairs; ++i) order[i] = i;
@@ -3060,7 +3078,7 @@ emdq_status fill_field_jobs(FieldJob *jobs, int n_pairs, const emdq_model *model
         emdq_model m = models[i];
         FieldJob &J = jobs[q];
         const int tiles_x = (r.w + kTile - 1) / kTile;
-        const int tiles_y = (r.h + kTile * kRowBlocks - 1) / (kTile * kRowBlocks);
+        const int tiles_y = (r.h + kTile * rows - 1) / (kTile * rows);
         const long long n_tiles = (r.w && r.h) ? (long long)tiles_x * tiles_y : 0;
         J.packed = m->packed;
         J.st = m->st;
@@ -3094,19 +3112,31 @@ emdq_status fill_field_jobs(FieldJob *jobs, int n_pairs, const emdq_model *model
 
 void launch_field_b(int mode, int variant, unsigned blocks, const FieldJob *jobs, int n_jobs,
                     hipStream_t stream) {
-#define EMDQ_FB(M, K)                                                                       \
-    hipLaunchKernelGGL((k_field_b<M, K>), dim3(blocks), dim3(kFieldThreads), 0, stream, jobs, \
+#define EMDQ_FB(M, K, R)                                                                       \
+    hipLaunchKernelGGL((k_field_b<M, K, R>), dim3(blocks), dim3(kFieldThreads), 0, stream, jobs, \
                        n_jobs)
     if (mode == kModeField) {
-        if (variant == 1) EMDQ_FB(kModeField, 2);
-        else if (variant == 2) EMDQ_FB(kModeField, 1);
-        else EMDQ_FB(kModeField, 4);
+        if (variant == 1) EMDQ_FB(kModeField, 2, 1);
+        else if (variant == 2) EMDQ_FB(kModeField, 1, 1);
+        else if (variant == 3) EMDQ_FB(kModeField, 4, 2);
+        else EMDQ_FB(kModeField, 4, 1);
     } else {
-        if (variant == 1) EMDQ_FB(kModeWarp, 2);
-        else if (variant == 2) EMDQ_FB(kModeWarp, 1);
-        else EMDQ_FB(kModeWarp, 4);
+        if (variant == 1) EMDQ_FB(kModeWarp, 2, 1);
+        else if (variant == 2) EMDQ_FB(kModeWarp, 1, 1);
+        else if (variant == 3) EMDQ_FB(kModeWarp, 4, 2);
+        else EMDQ_FB(kModeWarp, 4, 1);
     }
 #undef EMDQ_FB
+}
+
+// The batch's field-kernel shape: the one set by the autotuner or
+// emdq_batch_set_variant, else split-K 4 with the row blocks the single-pair
+// rule gives for the batch's total tile count.
+int batch_variant(emdq_batch b, int n_pairs, const emdq_region *regions) {
+    if (b->variant >= 0) return b->variant;
+    long long n64 = 0;
+    for (int i = 0; i < n_pairs; ++i) n64 += tiles64(regions[i].w, regions[i].h);
+    return field_row_blocks(n64) == 2 ? 3 : 0;
 }
 
 emdq_status batch_regions_ok(emdq_batch b, int n_pairs, const emdq_model *models,
@@ -3128,14 +3158,16 @@ emdq_status batch_field_launch(emdq_batch b, int n_pairs, const emdq_model *mode
     FieldJob *jobs = (FieldJob *)batch_slot(b, &slot);
     if (!jobs) return EMDQ_EHIP;
     long long blocks = 0;
-    rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[b->variant], &blocks);
+    const int v = batch_variant(b, n_pairs, regions);
+    rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[v], kVariantRows[v],
+                         &blocks);
     if (rc != EMDQ_OK) return rc;
     for (int i = 0; i < n_pairs; ++i) models[i]->last = stream;
     if (blocks == 0) return EMDQ_OK;
     EMDQ_HIP(hipMemcpyAsync(b->field_jobs, jobs, sizeof(FieldJob) * n_pairs,
                             hipMemcpyHostToDevice, stream));
     EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
-    launch_field_b(mode, b->variant, (unsigned)blocks, b->field_jobs, n_pairs, stream);
+    launch_field_b(mode, v, (unsigned)blocks, b->field_jobs, n_pairs, stream);
     return check_launch();
 }
 
@@ -3379,7 +3411,7 @@ emdq_status emdq_batch_autotune(emdq_batch b, int n_pairs, const emdq_model *mod
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc != EMDQ_OK) {
-            b->variant = 0;
+            b->variant = -1;
             return rc;
         }
         if (cache_path) {
@@ -3409,7 +3441,9 @@ emdq_status emdq_batch_prepare(emdq_batch b, int warp, int n_pairs, const emdq_m
     FieldJob *jobs = (FieldJob *)malloc(sizeof(FieldJob) * (size_t)n_pairs);
     if (!jobs) return EMDQ_ENOMEM;
     long long blocks = 0;
-    rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[b->variant], &blocks);
+    const int v = batch_variant(b, n_pairs, regions);
+    rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[v], kVariantRows[v],
+                         &blocks);
     if (rc == EMDQ_OK &&
         hipMemcpy(b->prepared, jobs, sizeof(FieldJob) * n_pairs, hipMemcpyHostToDevice) !=
             hipSuccess)
@@ -3421,7 +3455,7 @@ emdq_status emdq_batch_prepare(emdq_batch b, int warp, int n_pairs, const emdq_m
     }
     b->prep_mode = mode;
     b->prep_pairs = n_pairs;
-    b->prep_variant = b->variant;
+    b->prep_variant = v;
     b->prep_blocks = blocks;
     return EMDQ_OK;
 }
