@@ -40,9 +40,9 @@ METRIC = "Mpix/s dense EMDQ field+warp (N=2000); EM iters & px error learned vs 
 PEAK_TFLOPS = {"f32": 157.3, "f16": 2500.0, "bf16": 2500.0}
 # HBM traffic of the production field + warp kernel per launch, from rocprofv3
 # FETCH_SIZE + WRITE_SIZE (KiB per dispatch) scaled by the copy-kernel
-# calibration (factors 2.0 and 1.0): 15149.8 KiB x 2.0 + 18814.1 KiB x 1.0.
+# calibration (factors 2.0 and 1.0): 15149.4 KiB x 2.0 + 18814.1 KiB x 1.0.
 # Set to None whenever the kernel changes, until the counters are taken again.
-TRAFFIC_BYTES = round((15149.8 * 2.0 + 18814.1 * 1.0) * 1024)
+TRAFFIC_BYTES = round((15149.4 * 2.0 + 18814.1 * 1.0) * 1024)
 WORKLOADS = ("production", "fhd-f32", "fhd-f16", "fhd-bf16", "batch64", "batch64-learned")
 
 
