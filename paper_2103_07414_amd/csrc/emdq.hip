@@ -218,9 +218,9 @@ __device__ __forceinline__ float2 blend_displacement(float W, float Cd, float Sn
 //
 // Gaussian-inlier / uniform-outlier mixture of Sec. II-A.  Each E-step
 // workgroup leaves, for its rows, the FP64 sums (sum p_i, sum p_i e_i^2) in
-// row order; sum_partials adds them over the workgroups in a fixed order, so
-// every workgroup that finishes the iteration gets the same sigma^2 and gamma
-// and hence the same posteriors.
+// row order; partial_run and combine_partials add them over the workgroups
+// in a fixed order, so every workgroup that finishes the iteration gets the
+// same sigma^2 and gamma and hence the same posteriors.
 
 struct PostParams {
     double u, sigma2_min, gamma_min, gamma_max;
@@ -866,8 +866,8 @@ __global__ __launch_bounds__(kEmThreads) void k_estep_s(
 // Finishes an EM iteration of one pair (one workgroup of kPostThreads >=
 // kEmThreads threads; a batch pair, or a single pair in three launches per
 // iteration): the E-step partials summed as partial_run / combine_partials
-// do, sigma^2 and gamma, the posteriors (FP64) and mask of every match, and
-// the stop rule.  The same arithmetic as the posterior step at the start of
+// do, sigma^2 and gamma, the posteriors (post_p) and mask of every match,
+// and the stop rule.  The same arithmetic as the posterior step at the start of
 // a fused M-step, so every mode gives the same bits.  host_copy (pinned host
 // memory, may be null): the state as this kernel leaves it, so the host
 // reads the stop flag without a copy.
@@ -2635,7 +2635,8 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     ok = ok && hipMalloc((void **)&m->st, sizeof(DevState)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&m->host_st, sizeof(DevState), hipHostMallocDefault) ==
                    hipSuccess;
-    // coherent: the E-step kernel stores the stop flags straight into them
+    // coherent: the EM's E-step or posterior kernel stores the stop flags
+    // straight into them
     ok = ok && hipHostMalloc((void **)&m->em_st, 2 * sizeof(DevState), hipHostMallocCoherent) ==
                    hipSuccess;
     ok = ok && hipHostGetDevicePointer((void **)&m->em_st_dev, m->em_st, 0) == hipSuccess;
@@ -2718,8 +2719,8 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
     const PostParams pp{u, (double)prm.sigma2_min, (double)prm.gamma_min, (double)prm.gamma_max,
                         prm.p_thresh, prm.max_iter};
     // Up to kFusedMaxN matches the posterior step runs inside the M-step (two
-    // launches per iteration; every M-step workgroup forms all n posteriors
-    // in FP64); above it in its own one-workgroup kernel (three launches).
+    // launches per iteration; every M-step workgroup forms all n
+    // posteriors); above it in its own one-workgroup kernel (three launches).
     const bool fused = n <= kFusedMaxN;
     // M-step of iteration it (from 1); fused: the posteriors of iteration
     // it - 1 first, when it >= 2
