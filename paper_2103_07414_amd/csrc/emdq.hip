@@ -2739,6 +2739,7 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
     // chunk k is read while chunk k + 1 already runs, so the GPU does not
     // wait for the host between chunks.
     int enqueued = 0;
+    bool stopped = false;   // the host has read a stop flag
     for (int k = 0;; ++k) {
         // the chunk's last E-step (fused) or posterior kernel also stores the
         // state into host slot k & 1 (a chunk holds at least one iteration:
@@ -2764,15 +2765,18 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
         if (k > 0) {
             EMDQ_HIP(hipEventSynchronize(m->em_ev[(k - 1) & 1]));
             const DevState &prev = m->em_st[(k - 1) & 1];
-            if (prev.done || prev.status < 0) break;
+            if (prev.done || prev.status < 0) {
+                stopped = true;
+                break;
+            }
         }
         if (enqueued >= prm.max_iter) break;
     }
     // the fit with the final posteriors (fused: the posteriors of the last
-    // enqueued iteration first; nothing if the EM stopped earlier, as that
-    // M-step fitted already), then (fused) the last stop decision and the
-    // inliers packed
-    mstep(enqueued + 1, 1);
+    // enqueued iteration first; not needed once a stop flag was read, as the
+    // M-step before the stopping E-step fitted already), then (fused) the
+    // last stop decision and the inliers packed
+    if (!(fused && stopped)) mstep(enqueued + 1, 1);
     const EmFinal fin{fused ? m->chg : nullptr, (int)em_blocks, enqueued, prm.max_iter};
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, stream, m->xy, m->q,
                        m->s, m->mask, n, m->packed, m->xs, m->ys, m->st, fin);
