@@ -208,6 +208,34 @@ def test_batch_autotune_variants_and_cache(tmp_path):
         assert torch.equal(by_var[3][i], by_var[0][i]), i
 
 
+@pytest.mark.parametrize("n", [2047, 2048, 2049, 2050])
+def test_em_path_boundary(n):
+    """Single-pair fits switch from two launches per iteration (posterior in
+    the M-step) to three at 2049 matches.  Either side of the switch, on
+    1280 x 1024 pairs of that many matches: status, iterations and mask equal
+    the oracle's, and every result equals the batched fit's bits."""
+    torch = torch_or_skip()
+    E = emdq()
+    cfg = synth.PairConfig(1280, 1024, n, 0.3, 8, 15.0, 80.0)
+    P = synth.gen_pair(cfg, 7000 + n, with_frame=False)
+    src, dst = to_dev(P.src, torch), to_dev(P.dst, torch)
+    ref = O.fit(P.src, P.dst, 1280, 1024)
+    m = E.Model(n)
+    m.fit(src, dst, 1280, 1024)
+    mb = E.Model(n)
+    b = E.Batch(1)
+    b.fit([mb], [src], [dst], [(1280, 1024)])
+    r, rb = m.results(), mb.results()
+    print(f"n {n}: status {r['status']} iters {r['iters']} (oracle {ref.status}, {ref.iters})",
+          flush=True)
+    assert r["status"] == ref.status and r["iters"] == ref.iters
+    assert np.array_equal(r["mask"], ref.mask)
+    for key in ("status", "iters", "n_in", "sigma2", "gamma"):
+        assert r[key] == rb[key], key
+    for key in ("p", "q", "scale", "mask"):
+        assert np.array_equal(r[key], rb[key]), key
+
+
 def test_single_field_row_blocks_bit_identical():
     """A single-pair FP32 launch of at least 768 32 x 64 tiles takes two row
     blocks per wavefront: the 2048 x 1536 field of the production fit in one
