@@ -2008,12 +2008,24 @@ constexpr int kStartWaves = 8, kStartThreads = kStartWaves * kWave;
 static_assert(kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid + kNHid + 1 == 24961,
               "weight vector size stated in the header");
 
+// Neighbour search of pairs up to kGridMaxN matches: a uniform grid of at
+// most kGridDim x kGridDim cells over the bounding box of the finite source
+// points (about two per cell), counting-sorted into LDS by every workgroup.
+constexpr int kGridMaxN = 4096, kGridDim = 45, kGridMaxCells = kGridDim * kGridDim;
+
 struct alignas(16) StartLds {
     float w1t[kNFeat][kNHid];   // transposed: lane o reads w1t[k][o]
     float w2t[kNHid][kNHid];
     float b1[kNHid], b2[kNHid], w3[kNHid];
     float f[kStartWaves][kNFeat];
     float h[kStartWaves][kNHid];
+    float2 gp[kGridMaxN];        // points in cell order
+    uint16_t gi[kGridMaxN];      // their match indices
+    int gs[kGridMaxCells + 1];   // first point of every cell (counts while built)
+    float gbox[kStartWaves][4];  // bounding-box partials, then (x0, y0, sx, sy)
+    float gmargin;               // rounding allowance of the cell assignment
+    int gbad[kStartWaves];       // a non-finite point seen by the wavefront
+    int gdim[2];                 // nx, ny (nx = 0: no grid, every pair scanned)
 };
 
 __device__ __forceinline__ float gelu(float t) {
@@ -2029,6 +2041,11 @@ __device__ __forceinline__ double dist2_f64(float2 a, float2 b) {
 #pragma clang fp contract(off)
     const double dx = (double)b.x - (double)a.x, dy = (double)b.y - (double)a.y;
     return dx * dx + dy * dy;   // rounded as written, no fused multiply-add
+}
+
+// grid cell of a coordinate (the same arithmetic when sorting and searching)
+__device__ __forceinline__ int grid_cell(float v, float v0, float sv, int nv) {
+    return min((int)((v - v0) / sv), nv - 1);
 }
 
 
@@ -2059,26 +2076,190 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
         __syncthreads();
     }
 
+    // ---- grid of the source points (pairs up to kGridMaxN matches)
+    bool grid = n <= kGridMaxN;
+    if (grid) {
+        float lo_x = __builtin_huge_valf(), lo_y = __builtin_huge_valf();
+        float hi_x = -__builtin_huge_valf(), hi_y = -__builtin_huge_valf();
+        bool bad = false;
+        for (int j = tid; j < n; j += kStartThreads) {
+            const float2 v = src[j];
+            if (finite2(v)) {
+                lo_x = fminf(lo_x, v.x);
+                lo_y = fminf(lo_y, v.y);
+                hi_x = fmaxf(hi_x, v.x);
+                hi_y = fmaxf(hi_y, v.y);
+            } else {
+                bad = true;
+            }
+        }
+        const bool wave_bad = __any(bad);
+        for (int off = 32; off >= 1; off >>= 1) {
+            lo_x = fminf(lo_x, __shfl_xor(lo_x, off, kWave));
+            lo_y = fminf(lo_y, __shfl_xor(lo_y, off, kWave));
+            hi_x = fmaxf(hi_x, __shfl_xor(hi_x, off, kWave));
+            hi_y = fmaxf(hi_y, __shfl_xor(hi_y, off, kWave));
+        }
+        if (lane == 0) {
+            L.gbox[wave][0] = lo_x;
+            L.gbox[wave][1] = lo_y;
+            L.gbox[wave][2] = hi_x;
+            L.gbox[wave][3] = hi_y;
+            L.gbad[wave] = wave_bad ? 1 : 0;
+        }
+        for (int c = tid; c <= kGridMaxCells; c += kStartThreads) L.gs[c] = 0;
+        __syncthreads();
+        if (tid == 0) {
+            int any_bad = L.gbad[0];
+            for (int w = 1; w < kStartWaves; ++w) {
+                lo_x = fminf(lo_x, L.gbox[w][0]);
+                lo_y = fminf(lo_y, L.gbox[w][1]);
+                hi_x = fmaxf(hi_x, L.gbox[w][2]);
+                hi_y = fmaxf(hi_y, L.gbox[w][3]);
+                any_bad |= L.gbad[w];
+            }
+            int nx = 1, ny = 1;
+            float sx = 1.f, sy = 1.f;
+            if (lo_x <= hi_x) {   // some point is finite
+                const float ex = hi_x - lo_x, ey = hi_y - lo_y;
+                const float cells = fmaxf(1.f, 0.5f * (float)n);
+                float side = sqrtf(ex * ey / cells);
+                side = fmaxf(side, fmaxf(ex, ey) / (float)kGridDim);
+                if (side > 0.f) {
+                    nx = min(max((int)ceilf(ex / side), 1), kGridDim);
+                    ny = min(max((int)ceilf(ey / side), 1), kGridDim);
+                }
+                if (ex > 0.f) sx = ex / (float)nx;
+                if (ey > 0.f) sy = ey / (float)ny;
+            } else {
+                lo_x = lo_y = 0.f;
+            }
+            // a cell index below xa (above xb) puts a point left of x0 + xa sx
+            // (right of x0 + (xb + 1) sx) up to the rounding of the
+            // subtraction and the division: a few units in the last place of
+            // the coordinates, far inside this allowance
+            const float mag = fmaxf(fmaxf(fabsf(lo_x), fabsf(hi_x)), fmaxf(fabsf(lo_y), fabsf(hi_y)));
+            L.gmargin = 1e-4f * fmaxf(sx, sy) + 4e-6f * mag;
+            L.gbox[0][0] = lo_x;
+            L.gbox[0][1] = lo_y;
+            L.gbox[0][2] = sx;
+            L.gbox[0][3] = sy;
+            L.gdim[0] = any_bad ? 0 : nx;   // non-finite points: scan every pair
+            L.gdim[1] = ny;
+        }
+        __syncthreads();
+        grid = L.gdim[0] > 0;   // the same in every thread of the workgroup
+    }
+    if (grid) {
+        const float gx0 = L.gbox[0][0], gy0 = L.gbox[0][1], gsx = L.gbox[0][2], gsy = L.gbox[0][3];
+        const int gnx = L.gdim[0], gny = L.gdim[1];
+        for (int j = tid; j < n; j += kStartThreads) {   // counts
+            const float2 v = src[j];
+            if (finite2(v))
+                atomicAdd(&L.gs[grid_cell(v.y, gy0, gsy, gny) * gnx +
+                                grid_cell(v.x, gx0, gsx, gnx) + 1], 1);
+        }
+        __syncthreads();
+        if (wave == 0) {   // inclusive scan of the counts: gs[c] = first point of cell c
+            int carry = 0;
+            for (int c0 = 1; c0 <= gnx * gny; c0 += kWave) {
+                int v = c0 + lane <= gnx * gny ? L.gs[c0 + lane] : 0;
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const int u = __shfl_up(v, off, kWave);
+                    if (lane >= off) v += u;
+                }
+                if (c0 + lane <= gnx * gny) L.gs[c0 + lane] = v + carry;
+                carry += __shfl(v, kWave - 1, kWave);
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < n; j += kStartThreads) {   // scatter (order within a cell free)
+            const float2 v = src[j];
+            if (finite2(v)) {
+                const int c = grid_cell(v.y, gy0, gsy, gny) * gnx + grid_cell(v.x, gx0, gsx, gnx);
+                const int pos = atomicAdd(&L.gs[c], 1);
+                L.gp[pos] = v;
+                L.gi[pos] = (uint16_t)j;
+            }
+        }
+        __syncthreads();
+        // gs[c] now holds the end of cell c, i.e. the start of cell c + 1
+    }
+
     for (int i = block * kStartWaves + wave; i < n; i += nblocks * kStartWaves) {
         const float2 xi = src[i];
-        // ---- per-lane sorted lists of the 16 nearest (lanes scan j in
-        // increasing order, so an equal distance never displaces an entry)
+        // ---- per-lane sorted lists of the 16 nearest by (squared distance,
+        // index)
         double bd[kKnn];
         int bj[kKnn];
 #pragma unroll
         for (int k = 0; k < kKnn; ++k) { bd[k] = __builtin_huge_val(); bj[k] = 0x7fffffff; }
-        for (int j = lane; j < n; j += kWave) {
-            if (j == i) continue;
-            const double d2 = dist2_f64(xi, src[j]);
-            if (!(d2 < bd[kKnn - 1])) continue;
+        auto insert = [&](double d2, int j) {
+            if (!key_less(d2, j, bd[kKnn - 1], bj[kKnn - 1])) return;
 #pragma unroll
             for (int k = kKnn - 1; k >= 1; --k) {
-                const bool shift = bd[k - 1] > d2;
-                const bool here = !shift && bd[k] > d2;
+                const bool shift = key_less(d2, j, bd[k - 1], bj[k - 1]);
+                const bool here = !shift && key_less(d2, j, bd[k], bj[k]);
                 bd[k] = shift ? bd[k - 1] : (here ? d2 : bd[k]);
                 bj[k] = shift ? bj[k - 1] : (here ? j : bj[k]);
             }
-            if (bd[0] > d2) { bd[0] = d2; bj[0] = j; }
+            if (key_less(d2, j, bd[0], bj[0])) { bd[0] = d2; bj[0] = j; }
+        };
+        if (!grid) {
+            for (int j = lane; j < n; j += kWave)
+                if (j != i) insert(dist2_f64(xi, src[j]), j);
+        } else {
+            // Rings of cells around the match's cell, each ring searched
+            // whole, until 16 of the kept candidates lie closer than the
+            // nearest unsearched cell can: every point outside the searched
+            // square is at least the distance to its edge (less a margin for
+            // the rounding of the cell assignment).
+            const float gx0 = L.gbox[0][0], gy0 = L.gbox[0][1];
+            const float gsx = L.gbox[0][2], gsy = L.gbox[0][3];
+            const int gnx = L.gdim[0], gny = L.gdim[1];
+            const int cx = grid_cell(xi.x, gx0, gsx, gnx), cy = grid_cell(xi.y, gy0, gsy, gny);
+            const double margin = (double)L.gmargin;
+            auto range = [&](int a, int b) {   // points [a, b)
+                for (int q = a + lane; q < b; q += kWave) {
+                    const int j = L.gi[q];
+                    if (j != i) insert(dist2_f64(xi, L.gp[q]), j);
+                }
+            };
+            auto cell_start = [&](int c) { return c == 0 ? 0 : L.gs[c - 1]; };
+            auto row = [&](int y, int xa, int xb) {   // cells xa..xb of row y
+                range(cell_start(y * gnx + xa), L.gs[y * gnx + xb]);
+            };
+            for (int R = 0;; ++R) {
+                const int xa = max(cx - R, 0), xb = min(cx + R, gnx - 1);
+                const int ya = max(cy - R, 0), yb = min(cy + R, gny - 1);
+                if (R == 0) {
+                    row(cy, cx, cx);
+                } else {
+                    if (cy - R >= 0) row(cy - R, xa, xb);
+                    if (cy + R < gny) row(cy + R, xa, xb);
+                    for (int y = max(cy - R + 1, 0); y <= min(cy + R - 1, gny - 1); ++y) {
+                        if (cx - R >= 0) row(y, cx - R, cx - R);
+                        if (cx + R < gnx) row(y, cx + R, cx + R);
+                    }
+                }
+                if (xa == 0 && xb == gnx - 1 && ya == 0 && yb == gny - 1) break;   // all searched
+                double bound = __builtin_huge_val();
+                if (xa > 0) bound = fmin(bound, (double)xi.x - ((double)gx0 + (double)xa * gsx));
+                if (xb < gnx - 1)
+                    bound = fmin(bound, ((double)gx0 + (double)(xb + 1) * gsx) - (double)xi.x);
+                if (ya > 0) bound = fmin(bound, (double)xi.y - ((double)gy0 + (double)ya * gsy));
+                if (yb < gny - 1)
+                    bound = fmin(bound, ((double)gy0 + (double)(yb + 1) * gsy) - (double)xi.y);
+                bound -= margin;
+                if (bound > 0.0) {
+                    const double b2 = bound * bound;
+                    int cnt = 0;
+#pragma unroll
+                    for (int k = 0; k < kKnn; ++k) cnt += bd[k] < b2 ? 1 : 0;
+                    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
+                    if (cnt >= kKnn) break;
+                }
+            }
         }
         // ---- merge: 16 rounds of a wavefront arg-min over the list heads
         int my_nbr = -1;
