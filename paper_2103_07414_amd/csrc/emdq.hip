@@ -2026,6 +2026,8 @@ struct alignas(16) StartLds {
     float gmargin;               // rounding allowance of the cell assignment
     int gbad[kStartWaves];       // a non-finite point seen by the wavefront
     int gdim[2];                 // nx, ny (nx = 0: no grid, every pair scanned)
+    double kd[kStartWaves][kWave];   // candidates of the rank merge: distance
+    int kj[kStartWaves][kWave];      // and index
 };
 
 __device__ __forceinline__ float gelu(float t) {
@@ -2194,6 +2196,7 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
         int bj[kKnn];
 #pragma unroll
         for (int k = 0; k < kKnn; ++k) { bd[k] = __builtin_huge_val(); bj[k] = 0x7fffffff; }
+        double thresh = 0.0;   // grid search: the 16 nearest lie below it
         auto insert = [&](double d2, int j) {
             if (!key_less(d2, j, bd[kKnn - 1], bj[kKnn - 1])) return;
 #pragma unroll
@@ -2219,6 +2222,7 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
             const int gnx = L.gdim[0], gny = L.gdim[1];
             const int cx = grid_cell(xi.x, gx0, gsx, gnx), cy = grid_cell(xi.y, gy0, gsy, gny);
             const double margin = (double)L.gmargin;
+            thresh = __builtin_huge_val();
             auto range = [&](int a, int b) {   // points [a, b)
                 for (int q = a + lane; q < b; q += kWave) {
                     const int j = L.gi[q];
@@ -2257,14 +2261,56 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
 #pragma unroll
                     for (int k = 0; k < kKnn; ++k) cnt += bd[k] < b2 ? 1 : 0;
                     for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
-                    if (cnt >= kKnn) break;
+                    if (cnt >= kKnn) { thresh = b2; break; }
                 }
             }
         }
-        // ---- merge: 16 rounds of a wavefront arg-min over the list heads
         int my_nbr = -1;
+        bool merged = false;
+        if (grid) {
+            // ---- rank merge: the entries below the threshold (at least 16
+            // of them, or every candidate once the whole grid was searched)
+            // are gathered in LDS when they fit one per lane; each takes its
+            // rank by (distance, index) among them, and the 16 lowest ranks
+            // are the neighbours in order
+            int cl = 0;
+#pragma unroll
+            for (int k = 0; k < kKnn; ++k) cl += bd[k] < thresh ? 1 : 0;   // a prefix of the list
+            int pre = cl;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int u = __shfl_up(pre, off, kWave);
+                if (lane >= off) pre += u;
+            }
+            const int total = __shfl(pre, kWave - 1, kWave);
+            if (total <= kWave) {
+                const int base = pre - cl;
+#pragma unroll
+                for (int k = 0; k < kKnn; ++k)
+                    if (k < cl) {
+                        L.kd[wave][base + k] = bd[k];
+                        L.kj[wave][base + k] = bj[k];
+                    }
+                wave_sync();
+                int rank = kWave;
+                int mj = -1;
+                if (lane < total) {
+                    const double md = L.kd[wave][lane];
+                    mj = L.kj[wave][lane];
+                    rank = 0;
+                    for (int u = 0; u < total; ++u)
+                        rank += key_less(L.kd[wave][u], L.kj[wave][u], md, mj) ? 1 : 0;
+                }
+                wave_sync();
+                if (rank < kKnn) L.kj[wave][rank] = mj;   // ranks are distinct
+                wave_sync();
+                if (lane < min(total, kKnn)) my_nbr = L.kj[wave][lane];
+                wave_sync();
+                merged = true;
+            }
+        }
+        // ---- otherwise: 16 rounds of a wavefront arg-min over the list heads
 #pragma unroll 1
-        for (int r = 0; r < kKnn; ++r) {
+        for (int r = 0; r < (merged ? 0 : kKnn); ++r) {
             double md = bd[0];
             int mj = bj[0];
             for (int off = 32; off >= 1; off >>= 1) {
