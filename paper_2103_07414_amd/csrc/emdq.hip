@@ -2014,8 +2014,10 @@ static_assert(kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid + kNHid + 1 == 2496
 constexpr int kGridMaxN = 4096, kGridDim = 45, kGridMaxCells = kGridDim * kGridDim;
 
 struct alignas(16) StartLds {
-    float w1t[kNFeat][kNHid];   // transposed: lane o reads w1t[k][o]
-    float w2t[kNHid][kNHid];
+    // transposed (lane o reads w1t[k][o]); rows padded by one word so that
+    // the transposing stores of a wavefront fall in distinct banks
+    float w1t[kNFeat][kNHid + 1];
+    float w2t[kNHid][kNHid + 1];
     float b1[kNHid], b2[kNHid], w3[kNHid];
     float f[kStartWaves][kNFeat];
     float h[kStartWaves][kNHid];
@@ -2065,27 +2067,60 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
     if (!feat_out) {
         const float *W1 = wts, *B1 = W1 + kNHid * kNFeat, *W2 = B1 + kNHid;
         const float *B2 = W2 + kNHid * kNHid, *W3 = B2 + kNHid, *B3 = W3 + kNHid;
-        for (int t = tid; t < kNHid * kNFeat; t += kStartThreads)
-            L.w1t[t % kNFeat][t / kNFeat] = W1[t];
-        for (int t = tid; t < kNHid * kNHid; t += kStartThreads)
-            L.w2t[t % kNHid][t / kNHid] = W2[t];
+        // every load is issued before the first store (the pointer could
+        // alias LDS as far as the compiler knows, which would otherwise keep
+        // one load in flight at a time)
+        constexpr int kR1 = kNHid * kNFeat / kStartThreads, kR2 = kNHid * kNHid / kStartThreads;
+        static_assert(kR1 * kStartThreads == kNHid * kNFeat && kR2 * kStartThreads == kNHid * kNHid,
+                      "weight matrices split evenly over the threads");
+        float r1[kR1], r2[kR2];
+#pragma unroll
+        for (int k = 0; k < kR1; ++k) r1[k] = W1[tid + k * kStartThreads];
+#pragma unroll
+        for (int k = 0; k < kR2; ++k) r2[k] = W2[tid + k * kStartThreads];
+#pragma unroll
+        for (int k = 0; k < kR1; ++k) {
+            const int t = tid + k * kStartThreads;
+            L.w1t[t % kNFeat][t / kNFeat] = r1[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kR2; ++k) {
+            const int t = tid + k * kStartThreads;
+            L.w2t[t % kNHid][t / kNHid] = r2[k];
+        }
         for (int t = tid; t < kNHid; t += kStartThreads) {
             L.b1[t] = B1[t];
             L.b2[t] = B2[t];
             L.w3[t] = W3[t];
         }
         b3 = B3[0];
-        __syncthreads();
+        // the weights are complete at the grid's first barrier, or at this one
+        if (n > kGridMaxN) __syncthreads();
     }
 
-    // ---- grid of the source points (pairs up to kGridMaxN matches)
+    // ---- grid of the source points (pairs up to kGridMaxN matches); each
+    // thread keeps its points in registers for the three passes
+    constexpr int kPerThread = kGridMaxN / kStartThreads;
     bool grid = n <= kGridMaxN;
+    float2 pv[kPerThread];
     if (grid) {
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int j = tid + k * kStartThreads;
+            if (j < n) {
+                pv[k] = src[j];
+            } else {
+                pv[k].x = __builtin_huge_valf();   // beyond n: never used
+                pv[k].y = 0.f;
+            }
+        }
         float lo_x = __builtin_huge_valf(), lo_y = __builtin_huge_valf();
         float hi_x = -__builtin_huge_valf(), hi_y = -__builtin_huge_valf();
         bool bad = false;
-        for (int j = tid; j < n; j += kStartThreads) {
-            const float2 v = src[j];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            if (tid + k * kStartThreads >= n) continue;
+            const float2 v = pv[k];
             if (finite2(v)) {
                 lo_x = fminf(lo_x, v.x);
                 lo_y = fminf(lo_y, v.y);
@@ -2155,8 +2190,10 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
     if (grid) {
         const float gx0 = L.gbox[0][0], gy0 = L.gbox[0][1], gsx = L.gbox[0][2], gsy = L.gbox[0][3];
         const int gnx = L.gdim[0], gny = L.gdim[1];
-        for (int j = tid; j < n; j += kStartThreads) {   // counts
-            const float2 v = src[j];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {   // counts
+            if (tid + k * kStartThreads >= n) continue;
+            const float2 v = pv[k];
             if (finite2(v))
                 atomicAdd(&L.gs[grid_cell(v.y, gy0, gsy, gny) * gnx +
                                 grid_cell(v.x, gx0, gsx, gnx) + 1], 1);
@@ -2175,8 +2212,11 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
             }
         }
         __syncthreads();
-        for (int j = tid; j < n; j += kStartThreads) {   // scatter (order within a cell free)
-            const float2 v = src[j];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {   // scatter (order within a cell free)
+            const int j = tid + k * kStartThreads;
+            if (j >= n) continue;
+            const float2 v = pv[k];
             if (finite2(v)) {
                 const int c = grid_cell(v.y, gy0, gsy, gny) * gnx + grid_cell(v.x, gx0, gsx, gnx);
                 const int pos = atomicAdd(&L.gs[c], 1);
