@@ -87,6 +87,9 @@ constexpr int field_waves(int rb) { return rb == 1 ? kFieldWaves : 2; }
 #define EMDQ_EM_CHUNK 2
 #endif
 constexpr int kEmChunk = EMDQ_EM_CHUNK; // EM iterations enqueued between stop-flag reads
+#ifndef EMDQ_START_WGS
+#define EMDQ_START_WGS 2048   // batched learned start: workgroups over all pairs
+#endif
 #ifndef EMDQ_FUSED_MAX_N
 #define EMDQ_FUSED_MAX_N 2048
 #endif
@@ -3635,8 +3638,9 @@ emdq_status emdq_batch_learned_start(emdq_batch b, int n_pairs, const float *con
     EMDQ_HIP(hipMemcpyAsync(b->start_jobs, jobs, sizeof(StartJob) * n_pairs,
                             hipMemcpyHostToDevice, stream));
     EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
-    // enough workgroups per pair to cover the largest one; about 2048 in all
-    int per = (2048 + n_pairs - 1) / n_pairs;
+    // enough workgroups per pair to cover the largest one; about
+    // EMDQ_START_WGS in all
+    int per = (EMDQ_START_WGS + n_pairs - 1) / n_pairs;
     const int need = (max_n + kStartWaves - 1) / kStartWaves;
     if (per > need) per = need;
     hipLaunchKernelGGL(k_start_b, dim3((unsigned)per, (unsigned)n_pairs), dim3(kStartThreads), 0,
