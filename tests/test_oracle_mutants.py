@@ -50,6 +50,26 @@ MUTANTS = [
      "double s = ((double)w / ref_w + (double)h / ref_h);"),
     ("residual sign", "double ex = y[2 * i] - fx, ey = y[2 * i + 1] - fy;",
      "double ex = y[2 * i] + fx, ey = y[2 * i + 1] - fy;"),
+    ("E-step blend weighted by p squared",
+     "double w = exp(-alpha * (dx * dx + dy * dy)) * wt[j];",
+     "double w = exp(-alpha * (dx * dx + dy * dy)) * wt[j] * wt[j];"),
+    ("E-step blend with twice alpha",
+     "if (oracle_blend_at(n, x, scale, q, p, alpha, x[2 * i], x[2 * i + 1], &fx, &fy) != 0) {",
+     "if (oracle_blend_at(n, x, scale, q, p, 2.0 * alpha, x[2 * i], x[2 * i + 1], &fx, &fy) != 0) {"),
+    ("E-step called with twice alpha in the EM loop",
+     "oracle_estep(n, x, y, p, scale, q, alpha, e2);",
+     "oracle_estep(n, x, y, p, scale, q, 2.0 * alpha, e2);"),
+    ("final M-step with the final p dropped",
+     "oracle_mstep(n, x, y, p, alpha, scale, q);   /* fit with the final p */", ""),
+    ("displacement feature scale 4 instead of 8",
+     "double ex = (y[2 * j] - x[2 * j] - dix) / 8.0,",
+     "double ex = (y[2 * j] - x[2 * j] - dix) / 4.0,"),
+    ("displacement feature sign flipped",
+     "double ex = (y[2 * j] - x[2 * j] - dix) / 8.0,",
+     "double ex = (dix - (y[2 * j] - x[2 * j])) / 8.0,"),
+    ("displacement feature x and y swapped",
+     "f[4 * r + 2] = ex / (1.0 + fabs(ex));\n            f[4 * r + 3] = ey / (1.0 + fabs(ey));",
+     "f[4 * r + 2] = ey / (1.0 + fabs(ey));\n            f[4 * r + 3] = ex / (1.0 + fabs(ex));"),
 ]
 
 

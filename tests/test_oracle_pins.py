@@ -711,3 +711,155 @@ def test_start_grad_matches_torch_autograd_and_finite_differences():
         lp, _ = O.start_grad(f, y, w + e)
         lm, _ = O.start_grad(f, y, w - e)
         assert (lp - lm) / 2e-6 == pytest.approx(g[k], rel=1e-5, abs=1e-9)
+
+
+# ------------------------------------- E-step and the final M-step (Sec. II-A) --
+# The E-step blends every match's fit at x_i with the soft weights
+# exp(-alpha |x_i - x_j|^2) p_j (Eqs. (2)-(4)); the fit returned at the end is
+# one more M-step with the final posteriors.  These pins evaluate both by other
+# routes: 50-digit full-DQ blending, and a weighted similarity fit written from
+# numpy's SVD (Eq. (18)) instead of the oracle's closed-form angle.
+
+def fit_svd(x, y, w):
+    """Weighted similarity (s, R, t) with y ~ s (R x + t): Eq. (18) by SVD
+    with det correction, Eq. (19) norm ratio, Eq. (20) translation."""
+    S = w.sum()
+    xm = (w[:, None] * x).sum(0) / S
+    ym = (w[:, None] * y).sum(0) / S
+    a, b = x - xm, y - ym
+    U, _, Vt = np.linalg.svd((b * w[:, None]).T @ a)
+    R = U @ np.diag([1.0, np.linalg.det(U @ Vt)]) @ Vt
+    s = np.sqrt((w * (b ** 2).sum(1)).sum() / (w * (a ** 2).sum(1)).sum())
+    return s, R, ym / s - R @ xm
+
+
+def mstep_svd(x, y, p, alpha):
+    """Per-match fits with weights exp(-alpha |x_i - x_j|^2) p_j (Eq. (4))."""
+    out = []
+    for i in range(x.shape[0]):
+        d2 = ((x - x[i]) ** 2).sum(1)
+        out.append(fit_svd(x, y, np.exp(-alpha * d2) * p))
+    return out
+
+
+def assert_fits_equal(scale, q, fits, atol_t=1e-8):
+    for i, (s, R, t) in enumerate(fits):
+        ct, st, tx, ty = O.dq_decode(q[i])
+        assert scale[i] == pytest.approx(s, rel=1e-10), i
+        assert np.allclose([ct, st], [R[0, 0], R[1, 0]], atol=1e-10), i
+        assert np.allclose([tx, ty], t, atol=atol_t), i
+
+
+def _soft_case(seed, n=8):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 40, (n, 2))
+    th = rng.uniform(-0.2, 0.2)
+    y = 1.04 * (x @ rot(th).T + [3.0, -2.0]) + rng.normal(0, 1.5, (n, 2))
+    y[n - 1] += [25.0, -30.0]                      # one gross mismatch
+    p = rng.uniform(0.05, 1.0, n)                  # fractional posteriors
+    return x, y, p
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_estep_residuals_soft_weights_full_dq(seed):
+    """E-step residuals with fractional p against 50-digit full-DQ blending of
+    the fits with weights exp(-alpha d^2) p_j."""
+    mp.mp.dps = 50
+    rng = np.random.default_rng(seed + 100)
+    n = 8
+    x, thetas, ts, scale, q = _random_fits(rng, n)
+    y = x + rng.normal(0, 4, (n, 2))
+    p = rng.uniform(0.05, 1.0, n)
+    alpha = 2e-3
+    e2 = O.estep(x, y, p, scale, q, alpha)
+    for i in range(n):
+        fx, fy = blend_full(x, scale, thetas, ts, p, alpha, x[i, 0], x[i, 1])
+        want = (y[i, 0] - fx) ** 2 + (y[i, 1] - fy) ** 2
+        assert e2[i] == pytest.approx(want, rel=1e-9, abs=1e-12), i
+
+
+def test_estep_closed_form_single_similarity():
+    """Matches with p = 0 carry wild fits; every other fit is one similarity
+    T.  Whatever the weights, the blend at x_i is T, so e_i^2 = |y_i - T(x_i)|^2
+    with T applied as a matrix."""
+    rng = np.random.default_rng(31)
+    n = 30
+    x = rng.uniform(0, 300, (n, 2))
+    y = rng.uniform(0, 300, (n, 2))
+    sT, thT, tT = 0.97, 0.11, np.array([6.0, -4.0])
+    p = rng.uniform(0.2, 1.0, n)
+    scale = np.full(n, sT)
+    q = np.tile(O.dq_from_rt(thT, *tT), (n, 1))
+    wild = rng.choice(n, 8, replace=False)
+    p[wild] = 0.0
+    for j in wild:
+        scale[j] = rng.uniform(0.5, 2.0)
+        q[j] = O.dq_from_rt(rng.uniform(-2, 2), *rng.uniform(-300, 300, 2))
+    e2 = O.estep(x, y, p, scale, q, O.alpha(320, 240))
+    Tx = sT * (x @ rot(thT).T + tT)
+    assert np.allclose(e2, ((y - Tx) ** 2).sum(1), rtol=1e-11, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_fit_one_iteration_from_soft_start(seed):
+    """One EM iteration (max_iter = 1) from fractional starting posteriors,
+    rebuilt step by step by other routes: SVD fits with weights K_ij p_j,
+    50-digit full-DQ E-step residuals, sigma^2 and gamma from their
+    definitions, the posterior from scipy's Gaussian density and Bayes rule,
+    and the returned fit as the SVD fit with the new posteriors."""
+    mp.mp.dps = 50
+    x, y, p0 = _soft_case(seed)
+    n = x.shape[0]
+    W, H = 64, 48
+    alpha = 2e-3
+    prm = O.params(max_iter=1, alpha0=alpha, ref_w=W, ref_h=H)   # s = 1
+    f = O.fit(x, y, W, H, prm, init_p=p0)
+    assert f.status == O.WARN_NOT_CONVERGED and f.iters == 1
+    fits = mstep_svd(x, y, p0, alpha)
+    sc = np.array([s for s, _, _ in fits])
+    th = np.array([np.arctan2(R[1, 0], R[0, 0]) for _, R, _ in fits])
+    tt = np.array([t for _, _, t in fits])
+    e = np.zeros((n, 2))
+    for i in range(n):
+        e[i] = y[i] - np.array(blend_full(x, sc, th, tt, p0, alpha, x[i, 0], x[i, 1]))
+    e2 = (e ** 2).sum(1)
+    s2 = max(1e-2, (p0 * e2).sum() / (2 * p0.sum()))
+    g = min(max(p0.sum() / n, 0.05), 0.95)
+    assert f.sigma2 == pytest.approx(s2, rel=1e-9)
+    assert f.gamma == pytest.approx(g, rel=1e-12)
+    L = stats.multivariate_normal(mean=[0, 0], cov=s2 * np.eye(2)).pdf(e)
+    p1 = g * L / (g * L + (1 - g) / (W * H))
+    assert np.allclose(f.p, p1, rtol=1e-8, atol=1e-12)
+    assert not np.allclose(p1, p0, atol=1e-3)      # the final fit differs from the first
+    assert_fits_equal(f.scale, f.q, mstep_svd(x, y, p1, alpha))
+
+
+@pytest.mark.parametrize("pair", [1, 3])
+def test_fit_returns_the_mstep_of_the_final_posteriors(pair):
+    """Sec. II-A step 7: the fits returned by a converged EM are the weighted
+    similarity fits with weights K_ij p_j of the final p (SVD route)."""
+    P = synth.gen_config(1, pair, with_frame=False)
+    f = O.fit(P.src, P.dst, 320, 240)
+    assert f.status == 0
+    x, y = P.src.astype(np.float64), P.dst.astype(np.float64)
+    rows = np.arange(0, 200, 9)
+    fits = mstep_svd(x, y, f.p, f.alpha)
+    assert_fits_equal(f.scale[rows], f.q[rows], [fits[i] for i in rows], atol_t=1e-7)
+
+
+def test_init_features_displacement_columns_literal():
+    """Displacement features ss((d_j - d_i) / 8), ss(t) = t / (1 + |t|), on a
+    five-point layout with hand-chosen displacements; expected values written
+    out by hand (neighbour order: squared distance, then index)."""
+    src = np.array([[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1]], np.float64)
+    d = np.array([[0, 0], [8, -24], [-8, 0], [0, 8], [24, 4]], np.float64)
+    F = O.init_features(src, src + d, 1.0)
+    # match 0: neighbours 1, 2, 3, 4 (all at distance 1)
+    want0 = [0.5, -0.75, -0.5, 0.0, 0.0, 0.5, 0.75, 1.0 / 3.0]
+    got0 = F[0].reshape(16, 4)[:4, 2:].ravel()
+    assert np.allclose(got0, want0, atol=1e-15)
+    # match 1 at (1, 0): neighbours 0 (d^2 = 1), 3, 4 (d^2 = 2), 2 (d^2 = 4)
+    want1 = [[-1, 0, -0.5, 0.75], [-1, 1, -0.5, 0.8], [-1, -1, 2 / 3, 7 / 9],
+             [-2, 0, -2 / 3, 0.75]]
+    assert np.allclose(F[1].reshape(16, 4)[:4], want1, atol=1e-15)
+    assert not F[:, 16:].any()
