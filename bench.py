@@ -8,7 +8,13 @@ the mosaic canvas).
 
 Workloads (--workload):
   production  (default) 1280 x 1024 RGB uint8 frame, N = 2000 matches (30 %
-              outliers, 8 Gaussian bumps), 4096 x 4096 RGBA FP32 canvas, FP32
+              outliers, 8 Gaussian bumps), 4096 x 4096 RGBA FP32 canvas, FP32.
+              Outside the timed steps it also reports the learned EM start
+              against the plain one (EM iterations, inlier F1, px error) on
+              this pair and on a 1920 x 1080, N = 5000 pair (40 % outliers,
+              12 bumps of 25 px), and the 64-pair batch below three ways:
+              batched with the learned start, batched with the plain start,
+              and plain single-pair calls (frames/s and px error)
   fhd-f32 / fhd-f16 / fhd-bf16
               1920 x 1080 frame, N = 4000 (30 % outliers), 1920 x 1080 canvas,
               with the blend's GEMM operands in the named precision
@@ -43,6 +49,11 @@ PEAK_TFLOPS = {"f32": 157.3, "f16": 2500.0, "bf16": 2500.0}
 # calibration (factors 2.0 and 1.0): 15149.4 KiB x 2.0 + 18814.1 KiB x 1.0.
 # Set to None whenever the kernel changes, until the counters are taken again.
 TRAFFIC_BYTES = round((15149.4 * 2.0 + 18814.1 * 1.0) * 1024)
+# Average duration of the same launch in the committed kernel trace of this
+# command (profiles/k_field_warp_f32_1280x1024_n2000.md), beside the live
+# HIP-event duration the roofline fraction is computed from.
+PROFILE = dict(file="profiles/k_field_warp_f32_1280x1024_n2000.md", kernel="k_field<1, 4, 1>",
+               avg_launch_ms=0.21479)
 WORKLOADS = ("production", "fhd-f32", "fhd-f16", "fhd-bf16", "batch64", "batch64-learned")
 
 
@@ -74,56 +85,105 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes": n * 4}), flush=True)
 
 
-def cpu_baseline(pairs, min_seconds):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads(n):
+    """Sets the OpenMP thread count of the oracle's parallel loops (the
+    oracle is built with gcc -fopenmp, i.e. libgomp); returns the previous
+    maximum."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(int(n))
+    return prev
+
+
+def oracle_step(O, P):
+    """One whole oracle step of a pair: EM fit, then field, bilinear sample
+    and merge of every frame pixel into a zero canvas.  Returns (fit, fit s,
+    field+warp s)."""
+    W, H = P.cfg.width, P.cfg.height
+    canvas = np.zeros((H, W, 4))
+    t0 = time.perf_counter()
+    f = O.fit(P.src, P.dst, W, H)
+    t1 = time.perf_counter()
+    O.warp(P.src, f.scale, f.q, f.mask, f.alpha, P.frame, canvas, 0, 0, 0, 0, W, H)
+    t2 = time.perf_counter()
+    return f, t1 - t0, t2 - t1
+
+
+def cpu_baseline(pairs, min_seconds, single_thread):
     """The FP64 oracle on the host: whole steps of the workload's pairs (EM fit
     + field, warp and merge of every frame pixel), cycling over the pairs
-    until at least `min_seconds` have passed."""
+    until at least `min_seconds` have passed, on all host threads.  With
+    `single_thread`, one step each of the small (320x240, N=200) and the
+    production (1280x1024, N=2000) pair on one thread as well."""
     import oracle as O
+    from paper_2103_07414_amd import synth
     reps, px, t_fit, t_warp = 0, 0, 0.0, 0.0
     t_start = time.perf_counter()
     fits = []
     while True:
         P = pairs[reps % len(pairs)]
-        W, H = P.cfg.width, P.cfg.height
-        canvas = np.zeros((H, W, 4))
-        t0 = time.perf_counter()
-        f = O.fit(P.src, P.dst, W, H)
-        t1 = time.perf_counter()
-        O.warp(P.src, f.scale, f.q, f.mask, f.alpha, P.frame, canvas, 0, 0, 0, 0, W, H)
-        t2 = time.perf_counter()
+        f, a, b = oracle_step(O, P)
         if reps < len(pairs):
             fits.append(f)
         reps += 1
-        px += W * H
-        t_fit += t1 - t0
-        t_warp += t2 - t1
-        if t2 - t_start >= min_seconds:
+        px += P.cfg.width * P.cfg.height
+        t_fit += a
+        t_warp += b
+        if time.perf_counter() - t_start >= min_seconds:
             break
     total = t_fit + t_warp
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    threads = oracle_threads(1)
     first = pairs[0].cfg
-    return fits, dict(value=round(px / total / 1e6, 4), unit="Mpix/s", cores=threads,
-                      kind="oracle",
-                      sample=f"{reps} whole pair steps ({min(reps, len(pairs))}"
-                             f" distinct pairs, first {first.width}x{first.height} "
-                             f"N={first.n_matches}): EM fit {t_fit / reps * 1e3:.0f} ms + "
-                             f"field/warp/merge of every pixel {t_warp / reps * 1e3:.0f} ms "
-                             f"per pair; FP64, OpenMP, {total:.1f} s in total")
+    out = dict(value=round(px / total / 1e6, 4), unit="Mpix/s", cores=threads,
+               kind="oracle", cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+               sample=f"{reps} whole pair steps ({min(reps, len(pairs))}"
+                      f" distinct pairs, first {first.width}x{first.height} "
+                      f"N={first.n_matches}): EM fit {t_fit / reps * 1e3:.0f} ms + "
+                      f"field/warp/merge of every pixel {t_warp / reps * 1e3:.0f} ms "
+                      f"per pair; FP64, OpenMP on {threads} threads, {total:.1f} s in total")
+    try:
+        if single_thread:
+            one = {}
+            for name, cfg in (("small_320x240_n200", 1), ("production_1280x1024_n2000", 2)):
+                P = synth.gen_config(cfg, 1)
+                _, a, b = oracle_step(O, P)
+                one[name] = dict(fit_ms=round(a * 1e3, 2), field_warp_ms=round(b * 1e3, 2),
+                                 mpix_s=round(P.cfg.width * P.cfg.height / (a + b) / 1e6, 4))
+            out["single_thread"] = one
+    finally:
+        oracle_threads(threads)
+    return fits, out
 
 
-def learned_vs_plain(E, torch, P, model, src, dst, stream, reps=5):
-    """EM iterations, fit time and field error against the generator's
-    ground truth, plain start (p = 1) against the learned start (kNN + MLP
-    prior, emdq_learned_start + emdq_fit_from); outside the timed steps."""
+def learned_vs_plain(E, torch, P, stream, reps=5):
+    """EM iterations, inlier F1 and field error against the generator's ground
+    truth, plain start (p = 1) against the learned start (kNN + MLP prior,
+    emdq_learned_start + emdq_fit_from), on one pair; outside the timed
+    steps."""
+    dev = torch.device("cuda:0")
     W, H = P.cfg.width, P.cfg.height
+    model = E.Model(P.cfg.n_matches)
+    src, dst = torch.from_numpy(P.src).to(dev), torch.from_numpy(P.dst).to(dev)
     weights = E.load_start_weights()
-    p0 = torch.empty(P.cfg.n_matches, dtype=torch.float32, device="cuda")
+    p0 = torch.empty(P.cfg.n_matches, dtype=torch.float32, device=dev)
     rng = np.random.default_rng(11)
     ix, iy = rng.integers(0, W, 4000), rng.integers(0, H, 4000)
     truth_px = P.truth_map(np.stack([ix, iy], 1).astype(np.float64))
-    fld = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+    fld = torch.empty((H, W, 2), dtype=torch.float32, device=dev)
     res = {}
-    for name in ("learned", "plain"):   # the model ends with the plain fit
+    for name in ("learned", "plain"):
         ts = []
         for _ in range(reps):
             torch.cuda.synchronize()
@@ -139,51 +199,137 @@ def learned_vs_plain(E, torch, P, model, src, dst, stream, reps=5):
         model.field(0, 0, W, H, fld, stream=stream)
         f = fld.cpu().numpy()[iy, ix].astype(np.float64)
         e = np.sqrt(np.sum((f - truth_px) ** 2, 1))
-        res[name] = dict(em_iters=r["iters"], fit_ms=round(float(np.median(ts)) * 1e3, 4),
+        res[name] = dict(em_iters=r["iters"], status=r["status"],
+                         fit_ms=round(float(np.median(ts)) * 1e3, 4),
                          n_inliers=r["n_in"], px_err_vs_truth_rms=round(float(np.sqrt(np.mean(e ** 2))), 4),
                          px_err_vs_truth_max=round(float(e.max()), 4),
                          mask_f1_vs_truth=round(float(2 * np.sum(r["mask"].astype(bool) & P.inlier)
                                                       / (r["mask"].sum() + P.inlier.sum())), 5))
+    model.close()
+    res["pair"] = dict(frame=[W, H], n_matches=P.cfg.n_matches, outliers=P.cfg.outlier_rate,
+                       bumps=[P.cfg.n_bumps, P.cfg.bump_amp, P.cfg.bump_sigma], seed=P.seed)
     res["start"] = "16-NN features, 64-128-128-1 GELU MLP trained on synthetic pairs (start_mlp.npy)"
     return res
 
 
-def truth_error(torch, pairs, models):
-    """Mean over pairs of the rms field error against the generator's truth
-    at 2000 sampled pixels per pair."""
-    errs = []
-    for P, m in zip(pairs, models):
-        W, H = P.cfg.width, P.cfg.height
-        rng = np.random.default_rng(P.seed)
-        ix, iy = rng.integers(0, W, 2000), rng.integers(0, H, 2000)
-        fld = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
-        m.field(0, 0, W, H, fld)
-        f = fld.cpu().numpy()[iy, ix].astype(np.float64)
-        t = P.truth_map(np.stack([ix, iy], 1).astype(np.float64))
-        errs.append(np.sqrt(np.mean(np.sum((f - t) ** 2, 1))))
-    return round(float(np.mean(errs)), 4)
+class Pairs:
+    """Device copies of a list of pairs, a model and a canvas each, and the
+    step functions that run them through the library."""
+
+    def __init__(self, E, torch, pairs, prec="f32"):
+        from paper_2103_07414_amd import synth
+        dev = torch.device("cuda:0")
+        self.E, self.torch, self.pairs = E, torch, pairs
+        self.models = [E.Model(P.cfg.n_matches) for P in pairs]
+        for m in self.models:
+            m.set_precision(prec)
+        self.srcs = [torch.from_numpy(P.src).to(dev) for P in pairs]
+        self.dsts = [torch.from_numpy(P.dst).to(dev) for P in pairs]
+        self.frames = [torch.from_numpy(P.frame).to(dev) for P in pairs]
+        self.layouts = [synth.canvas_layout(P.cfg) for P in pairs]
+        self.canvases = [torch.zeros((ch, cw, 4), dtype=torch.float32, device=dev)
+                         for cw, ch, _, _ in self.layouts]
+        self.sizes = [(P.cfg.width, P.cfg.height) for P in pairs]
+        self.batch = None
+        self.start_w = None
+        self.starts = None
+
+    def use_batch(self, learned):
+        E, torch = self.E, self.torch
+        self.batch = self.batch or E.Batch(len(self.pairs))
+        if learned and self.start_w is None:
+            self.start_w = E.load_start_weights()
+            self.starts = [torch.empty(P.cfg.n_matches, dtype=torch.float32, device="cuda")
+                           for P in self.pairs]
+        self.learned = learned
+
+    def fit(self, stream):
+        if self.batch is None:
+            for m, s_, d_, (w, h) in zip(self.models, self.srcs, self.dsts, self.sizes):
+                m.fit(s_, d_, w, h, stream=stream)
+        elif self.learned:
+            self.batch.learned_start(self.srcs, self.dsts, self.sizes, self.start_w,
+                                     self.starts, stream=stream)
+            self.batch.fit(self.models, self.srcs, self.dsts, self.sizes, stream=stream,
+                           init_ps=self.starts)
+        else:
+            self.batch.fit(self.models, self.srcs, self.dsts, self.sizes, stream=stream)
+
+    def warp(self, stream):
+        if self.batch is None:
+            for m, f_, c_, (cw, ch, ox, oy), (w, h) in zip(self.models, self.frames,
+                                                            self.canvases, self.layouts,
+                                                            self.sizes):
+                m.warp(f_, c_, ox, oy, 0, 0, w, h, stream=stream)
+        else:
+            self.batch.warp(self.models, self.frames, self.canvases,
+                            [(ox, oy) for _, _, ox, oy in self.layouts],
+                            [(0, 0, w, h) for w, h in self.sizes], stream=stream)
+
+    def step(self, stream, ev=None):
+        self.fit(stream)
+        if ev is not None:
+            ev[0].record(stream)
+        self.warp(stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    def frames_per_s(self, stream, steps):
+        """Whole steps (fit + warp of every pair), timed on the wall clock."""
+        torch = self.torch
+        self.step(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step(stream)
+        torch.cuda.synchronize()
+        return len(self.pairs) * steps / (time.perf_counter() - t0)
+
+    def truth_error(self):
+        """Mean over pairs of the rms field error against the generator's
+        truth at 2000 sampled pixels per pair."""
+        torch = self.torch
+        errs = []
+        for P, m in zip(self.pairs, self.models):
+            W, H = P.cfg.width, P.cfg.height
+            rng = np.random.default_rng(P.seed)
+            ix, iy = rng.integers(0, W, 2000), rng.integers(0, H, 2000)
+            fld = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+            m.field(0, 0, W, H, fld)
+            f = fld.cpu().numpy()[iy, ix].astype(np.float64)
+            t = P.truth_map(np.stack([ix, iy], 1).astype(np.float64))
+            errs.append(np.sqrt(np.mean(np.sum((f - t) ** 2, 1))))
+        return round(float(np.mean(errs)), 4)
+
+    def close(self):
+        for m in self.models:
+            m.close()
+        if self.batch is not None:
+            self.batch.close()
 
 
-def plain_sequential(E, torch, pairs, srcs, dsts, frames, canvases, layouts, sizes, stream,
-                     reps=3):
-    """The same pairs through plain single-pair calls (emdq_fit with p = 1,
-    then emdq_warp), one pair after the other: frames/s and field error."""
-    models = [E.Model(P.cfg.n_matches) for P in pairs]
-
-    def run():
-        for m, s_, d_, f_, c_, (cw, ch, ox, oy), (w, h) in zip(models, srcs, dsts, frames,
-                                                                canvases, layouts, sizes):
-            m.fit(s_, d_, w, h, stream=stream)
-            m.warp(f_, c_, ox, oy, 0, 0, w, h, stream=stream)
-    run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        run()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return dict(frames_per_s=round(len(pairs) * reps / wall, 2),
-                px_err_vs_truth_rms_mean=truth_error(torch, pairs, models))
+def batch_forms(E, torch, pairs, stream, steps=5):
+    """The 64 mixed pairs three ways, on the same GPU: the batched entry
+    points with the learned start, the batched entry points with the plain
+    start, and plain single-pair calls (emdq_fit with p = 1, then emdq_warp,
+    one pair after the other).  frames/s of whole steps and the mean field
+    error against the generator's truth."""
+    out = {}
+    for name, batched, learned in (("learned_batched", True, True),
+                                   ("plain_batched", True, False),
+                                   ("plain_single_pair_calls", False, False)):
+        R = Pairs(E, torch, pairs)
+        if batched:
+            R.use_batch(learned)
+        fps = R.frames_per_s(stream, steps)
+        res = [m.results() for m in R.models]
+        out[name] = dict(frames_per_s=round(fps, 2), px_err_vs_truth_rms_mean=R.truth_error(),
+                         em_iters_max=max(r["iters"] for r in res),
+                         em_iters_mean=round(float(np.mean([r["iters"] for r in res])), 2))
+        R.close()
+    out["learned_batched_over_plain_single"] = round(
+        out["learned_batched"]["frames_per_s"] / out["plain_single_pair_calls"]["frames_per_s"], 3)
+    return out
 
 
 def main():
@@ -211,42 +357,13 @@ def main():
         pairs = synth.gen_batch(64)
     else:
         pairs = [synth.gen_config(2 if wl == "production" else 4, args.pair)]
-    models = [E.Model(P.cfg.n_matches) for P in pairs]
-    for m in models:
-        m.set_precision(prec)
-    srcs = [torch.from_numpy(P.src).to(dev) for P in pairs]
-    dsts = [torch.from_numpy(P.dst).to(dev) for P in pairs]
-    frames = [torch.from_numpy(P.frame).to(dev) for P in pairs]
-    layouts = [synth.canvas_layout(P.cfg) for P in pairs]
-    canvases = [torch.zeros((ch, cw, 4), dtype=torch.float32, device=dev)
-                for cw, ch, _, _ in layouts]
-    sizes = [(P.cfg.width, P.cfg.height) for P in pairs]
-    batch = E.Batch(len(pairs)) if batched else None
-    if learned:
-        start_w = E.load_start_weights()
-        starts = [torch.empty(P.cfg.n_matches, dtype=torch.float32, device=dev) for P in pairs]
-
-    def step(ev=None):
-        if learned:
-            batch.learned_start(srcs, dsts, sizes, start_w, starts, stream=stream)
-            batch.fit(models, srcs, dsts, sizes, stream=stream, init_ps=starts)
-        elif batch is not None:
-            batch.fit(models, srcs, dsts, sizes, stream=stream)
-        else:
-            models[0].fit(srcs[0], dsts[0], *sizes[0], stream=stream)
-        if ev is not None:
-            ev[0].record(stream)
-        if batch is not None:
-            batch.warp(models, frames, canvases, [(ox, oy) for _, _, ox, oy in layouts],
-                       [(0, 0, w, h) for w, h in sizes], stream=stream)
-        else:
-            cw, ch, ox, oy = layouts[0]
-            models[0].warp(frames[0], canvases[0], ox, oy, 0, 0, *sizes[0], stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
+    R = Pairs(E, torch, pairs, prec)
+    if batched:
+        R.use_batch(learned)
+    models, sizes, layouts = R.models, R.sizes, R.layouts
 
     for _ in range(args.warmup):
-        step()
+        R.step(stream)
     torch.cuda.synchronize()
     res = [m.results() for m in models]
     for r in res:
@@ -258,7 +375,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(events[k])
+        R.step(stream, events[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     warp_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
@@ -269,12 +386,17 @@ def main():
     peak = PEAK_TFLOPS[prec]
     kernel = {"f32": "k_field<warp>", "f16": "k_field_half<warp,f16>",
               "bf16": "k_field_half<warp,bf16>"}[prec]
-    if batch is not None:
+    if batched:
         kernel = "k_field_b<warp>"
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4),
                     traffic=TRAFFIC_BYTES if wl == "production" else None, kernel=kernel,
-                    algorithmic_flops_per_launch=flops, avg_launch_ms=round(warp_ms, 5))
+                    algorithmic_flops_per_launch=flops, avg_launch_ms=round(warp_ms, 5),
+                    duration_source="HIP events recorded around every warp launch on the "
+                                    "stream it runs on, mean over the timed steps")
+    if wl == "production":
+        roofline["profile"] = dict(PROFILE, frac_at_profile_duration=round(
+            flops / (PROFILE["avg_launch_ms"] * 1e-3) / 1e12 / peak, 4))
     ms_per_step = wall / args.steps * 1e3
     if wl == "production":
         workload = ("single frame pair, plain EMDQ at production size: 1280x1024 RGB uint8 "
@@ -297,20 +419,24 @@ def main():
     out = dict(metric=METRIC, value=round(pix * args.steps / wall / 1e6, 3), unit="Mpix/s",
                n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype=prec if prec != "f32" else "f32", data="synthetic",
+               vs_baseline=None, dtype=prec, data="synthetic",
                config=cfg, warp_only_mpix_s=round(pix / (warp_ms * 1e-3) / 1e6, 2),
                fit_ms=round(ms_per_step - warp_ms, 4), roofline=roofline, learned_init=None)
     if wl == "production":
-        out["learned_init"] = learned_vs_plain(E, torch, pairs[0], models[0], srcs[0], dsts[0],
-                                               stream)
+        out["learned_init"] = learned_vs_plain(E, torch, pairs[0], stream)
+        out["learned_init_fhd_n5000"] = learned_vs_plain(E, torch, synth.gen_config(5, 1),
+                                                         stream)
+        out["batch64"] = batch_forms(E, torch, synth.gen_batch(64), stream)
     if batched:
         out["this_form"] = dict(frames_per_s=round(len(pairs) * args.steps / wall, 2),
-                                px_err_vs_truth_rms_mean=truth_error(torch, pairs, models))
-        out["plain_single_pair_calls"] = plain_sequential(E, torch, pairs, srcs, dsts, frames,
-                                                          canvases, layouts, sizes, stream)
+                                px_err_vs_truth_rms_mean=R.truth_error())
+        S = Pairs(E, torch, pairs)
+        out["plain_single_pair_calls"] = dict(frames_per_s=round(S.frames_per_s(stream, 3), 2),
+                                              px_err_vs_truth_rms_mean=S.truth_error())
+        S.close()
     if not args.no_cpu_baseline:
         sample = pairs[:1] if len(pairs) == 1 else pairs[:4]
-        fits, cpu = cpu_baseline(sample, args.cpu_seconds)
+        fits, cpu = cpu_baseline(sample, args.cpu_seconds, single_thread=wl == "production")
         out["cpu_baseline"] = cpu
         # px error of the GPU field against the oracle on sampled pixels of
         # the first pair, and mask agreement of the sampled pairs
@@ -326,6 +452,7 @@ def main():
         out["px_err_vs_oracle"] = float(np.abs(got - want).max())
         out["mask_equal_oracle"] = bool(all(np.array_equal(r["mask"], g.mask)
                                             for r, g in zip(res, fits)))
+    R.close()
     print(json.dumps(out), flush=True)
 
 

@@ -98,8 +98,10 @@ float emdq_alpha(const emdq_params *p, int frame_w, int frame_h);
  * EINVAL if out is null or n_max < 2; ENOMEM / EHIP on allocation failure. */
 emdq_status emdq_model_create(int n_max, emdq_model *out);
 
-/* Releases the model and its device memory (waits for its last stream).
- * Null is ignored. */
+/* Releases the model and its device memory.  It first waits for all work
+ * queued on the model's device (the model keeps no handle of the caller's
+ * streams, so a stream destroyed before the model is not touched).  Null is
+ * ignored. */
 void emdq_model_free(emdq_model m);
 
 /* EMDQ fit (Sec. II-A; Eqs. (1), (4), (18)-(20)).

@@ -2741,7 +2741,6 @@ struct emdq_model_s {
     DevState *em_st = nullptr;     // pinned [2]: stop flags read while the EM runs on
     DevState *em_st_dev = nullptr; // the same two slots, as the device addresses them
     hipEvent_t em_ev[2] = {};
-    hipStream_t last = nullptr;
 };
 
 namespace {
@@ -2928,7 +2927,15 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
 
 void emdq_model_free(emdq_model m) {
     if (!m) return;
-    if (m->last) (void)hipStreamSynchronize(m->last);
+    // Work still queued on the model's buffers is waited for by device, not
+    // by the caller's stream: that stream may already be destroyed when the
+    // model is released (garbage collection, process teardown), so the
+    // model keeps no stream handle at all.
+    int prev = 0;
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(m->device) == hipSuccess) {
+        (void)hipDeviceSynchronize();
+        (void)hipSetDevice(prev);
+    }
     (void)hipFree(m->xy);
     (void)hipFree(m->p);
     (void)hipFree(m->mask);
@@ -2968,7 +2975,6 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
     if (!params_ok(prm) || frame_w <= 0 || frame_h <= 0) return EMDQ_EINVAL;
     if (n < 2) return EMDQ_ETOOFEW;
     if (n > m->n_max) return EMDQ_EINVAL;
-    m->last = stream;
     m->n = n;
     const double alpha = alpha_d(prm, frame_w, frame_h);
     m->alpha = (float)alpha;
@@ -3062,7 +3068,6 @@ emdq_status emdq_model_set_nodes(emdq_model m, const float *x_xy, const float *s
                                  hipStream_t stream) {
     if (!m || !x_xy || !scale || !q || n < 1 || n > m->n_max || !(alpha > 0.f))
         return EMDQ_EINVAL;
-    m->last = stream;
     m->n = n;
     m->alpha = alpha;
     float4 *hxy = (float4 *)malloc((size_t)n * sizeof(float4));
@@ -3102,7 +3107,6 @@ emdq_status emdq_field(emdq_model m, int zx0, int zy0, int w, int h, float *out_
                        hipStream_t stream) {
     if (!m || !out_xy || w < 0 || h < 0) return EMDQ_EINVAL;
     if (w == 0 || h == 0) return EMDQ_OK;
-    m->last = stream;
     return launch_field(m, kModeField, zx0, zy0, w, h, (float2 *)out_xy, nullptr, 0, 0, 0,
                         nullptr, 0, 0, 0, stream);
 }
@@ -3118,7 +3122,6 @@ emdq_status emdq_warp(emdq_model m, const uint8_t *frame_rgb, int fw, int fh,
     if (w == 0 || h == 0) return EMDQ_OK;
     const long long cx0 = (long long)zx0 + ox, cy0 = (long long)zy0 + oy;
     if (cx0 < 0 || cy0 < 0 || cx0 + w > cw || cy0 + h > ch) return EMDQ_EINVAL;
-    m->last = stream;
     return launch_field(m, kModeWarp, zx0, zy0, w, h, nullptr, frame_rgb, fw, fh,
                         frame_pitch_bytes, (float4 *)canvas, canvas_pitch_px, ox, oy, stream);
 }
@@ -3129,7 +3132,6 @@ emdq_status emdq_track_nodes(emdq_model m, float beta, int n_nodes, float *pos_x
     if (n_nodes == 0) return EMDQ_OK;
     if (!pos_xy || !scale || !q || !sigma2) return EMDQ_EINVAL;
     if ((((uintptr_t)pos_xy) & 7u) || (((uintptr_t)q) & 15u)) return EMDQ_EINVAL;
-    m->last = stream;
     const float nal2 = -m->alpha * kLog2e;
     const unsigned blocks = (unsigned)((n_nodes + kRowsPerBlock - 1) / kRowsPerBlock);
     hipLaunchKernelGGL(k_track, dim3(blocks), dim3(kEmThreads), 0, stream, m->packed, m->st,
@@ -3144,7 +3146,6 @@ emdq_status emdq_uncertainty(emdq_model m, float beta, int zx0, int zy0, int w, 
     if (w == 0 || h == 0) return EMDQ_OK;
     const long long tx = (w + kUTile - 1) / kUTile, ty = (h + kUTile - 1) / kUTile;
     if (tx * ty > 0x7fffffffLL) return EMDQ_EINVAL;
-    m->last = stream;
     hipLaunchKernelGGL(k_uncertainty, dim3((unsigned)(tx * ty)), dim3(kUThreads), 0, stream,
                        m->packed, m->st, beta, zx0, zy0, w, h, (int)tx, out);
     return check_launch();
@@ -3437,7 +3438,6 @@ emdq_status batch_field_launch(emdq_batch b, int n_pairs, const emdq_model *mode
     rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[v], kVariantRows[v],
                          &blocks);
     if (rc != EMDQ_OK) return rc;
-    for (int i = 0; i < n_pairs; ++i) models[i]->last = stream;
     if (blocks == 0) return EMDQ_OK;
     EMDQ_HIP(hipMemcpyAsync(b->field_jobs, jobs, sizeof(FieldJob) * n_pairs,
                             hipMemcpyHostToDevice, stream));
@@ -3542,7 +3542,6 @@ emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
         const double alpha = alpha_d(prm, frame_w[i], frame_h[i]);
         m->n = n[i];
         m->alpha = (float)alpha;
-        m->last = stream;
         EmJob &J = jobs[i];
         J.src = (const float2 *)src_xy[i];
         J.dst = (const float2 *)dst_xy[i];

@@ -8,8 +8,11 @@ the library is missing, importing the functions fails loudly.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libemdq.so")
 
@@ -57,6 +60,32 @@ class EmdqError(RuntimeError):
 
 
 _lib = None
+
+# Models and batches still open.  They are released by an exit handler,
+# which runs before the interpreter (and torch, and the HIP runtime after it)
+# starts tearing down; a release that would only happen during that teardown
+# is skipped instead (the process is ending and the driver reclaims the
+# memory), so no HIP call runs after the runtime has begun to shut down.
+_open = weakref.WeakSet()
+
+
+def _close_open():
+    for obj in list(_open):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+def _release(obj):
+    """__del__ of Model and Batch: release unless the interpreter is
+    already finalising."""
+    if sys.is_finalizing():
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
 
 
 def lib():
@@ -132,6 +161,7 @@ def lib():
         L.emdq_status_string.argtypes = [I]
         L.emdq_status_string.restype = C.c_char_p
         _lib = L
+        atexit.register(_close_open)
     return _lib
 
 
@@ -385,6 +415,7 @@ class Model:
     def __init__(self, n_max: int):
         self.handle = emdq_model_create(n_max)
         self.n = 0
+        _open.add(self)
 
     def fit(self, src, dst, frame_w, frame_h, params=None, stream=None):
         self.n = int(src.shape[0])
@@ -423,12 +454,10 @@ class Model:
         if self.handle:
             emdq_model_free(self.handle)
             self.handle = None
+        _open.discard(self)
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)
 
 
 class Batch:
@@ -439,6 +468,7 @@ class Batch:
         _check(lib().emdq_batch_create(int(max_pairs), C.byref(h)), "emdq_batch_create")
         self.handle = h.value
         self.max_pairs = int(max_pairs)
+        _open.add(self)
 
     @staticmethod
     def _handles(models):
@@ -500,13 +530,7 @@ class Batch:
 
     def field(self, models, rects, outs, stream=None):
         """rects: list of (zx0, zy0, w, h); outs: CUDA float32 [h, w, 2]."""
-        import torch
-        regs = (Region * len(models))()
-        for r, (zx0, zy0, w, h), o in zip(regs, rects, outs):
-            if tuple(o.shape) != (h, w, 2):
-                raise ValueError("out must be [h, w, 2]")
-            r.zx0, r.zy0, r.w, r.h = zx0, zy0, w, h
-            r.out_xy = _dev(o, torch.float32, "out")
+        regs = self._field_regions(models, rects, outs)
         return _check(lib().emdq_batch_field(self.handle, len(models), self._handles(models),
                                              regs, _stream(stream)), "emdq_batch_field")
 
@@ -577,19 +601,7 @@ class Batch:
     def warp(self, models, frames, canvases, offsets, rects, stream=None):
         """frames: CUDA uint8 [fh, fw, 3]; canvases: CUDA float32 [ch, cw, 4];
         offsets: (ox, oy); rects: (zx0, zy0, w, h)."""
-        import torch
-        regs = (Region * len(models))()
-        for r, f, c, (ox, oy), (zx0, zy0, w, h) in zip(regs, frames, canvases, offsets, rects):
-            if f.dim() != 3 or f.shape[2] != 3 or c.dim() != 3 or c.shape[2] != 4:
-                raise ValueError("frame must be [fh, fw, 3] and canvas [ch, cw, 4]")
-            r.zx0, r.zy0, r.w, r.h = zx0, zy0, w, h
-            r.frame_rgb = _dev(f, torch.uint8, "frame")
-            r.fh, r.fw = int(f.shape[0]), int(f.shape[1])
-            r.frame_pitch_bytes = 3 * r.fw
-            r.canvas = _dev(c, torch.float32, "canvas")
-            r.ch, r.cw = int(c.shape[0]), int(c.shape[1])
-            r.canvas_pitch_px = r.cw
-            r.ox, r.oy = ox, oy
+        regs = self._warp_regions(models, frames, canvases, offsets, rects)
         return _check(lib().emdq_batch_warp(self.handle, len(models), self._handles(models),
                                             regs, _stream(stream)), "emdq_batch_warp")
 
@@ -597,9 +609,7 @@ class Batch:
         if self.handle:
             lib().emdq_batch_free(self.handle)
             self.handle = None
+        _open.discard(self)
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)

@@ -292,3 +292,55 @@ def test_batch_prepared_launch_in_a_graph():
         torch.cuda.synchronize()
         for i in range(len(pairs)):
             assert torch.equal(outs[i], eager[i]), (rep, i)
+
+
+def _batch64_against_oracle(torch, learned):
+    """The benchmarked batch of 64 mixed pairs (seed 3000) through the batched
+    entry points: every pair's status, iteration count and inlier mask equal
+    the oracle's, and its field is within the bar at 2000 sampled points."""
+    E = emdq()
+    pairs = synth.gen_batch(64, with_frame=False)
+    srcs = [to_dev(p.src, torch) for p in pairs]
+    dsts = [to_dev(p.dst, torch) for p in pairs]
+    sizes = [(p.cfg.width, p.cfg.height) for p in pairs]
+    mb = [E.Model(p.cfg.n_matches) for p in pairs]
+    b = E.Batch(64)
+    starts = None
+    if learned:
+        w = E.load_start_weights()
+        starts = [torch.empty(p.cfg.n_matches, dtype=torch.float32, device="cuda")
+                  for p in pairs]
+        b.learned_start(srcs, dsts, sizes, w, starts)
+        wo = np.load(E.START_WEIGHTS, allow_pickle=False).astype(np.float64)
+    b.fit(mb, srcs, dsts, sizes, init_ps=starts)
+    rects = [(0, 0, w_, h_) for w_, h_ in sizes]
+    outs = [torch.empty((h_, w_, 2), dtype=torch.float32, device="cuda") for w_, h_ in sizes]
+    b.field(mb, rects, outs)
+    worst = 0.0
+    for i, (p, m, o) in enumerate(zip(pairs, mb, outs)):
+        W, H = sizes[i]
+        init = None
+        if learned:
+            init = O.init_mlp(O.init_features(p.src, p.dst, O.alpha(W, H)), wo)
+        ref = O.fit(p.src, p.dst, W, H, init_p=init)
+        r = m.results()
+        assert r["status"] == ref.status and r["iters"] == ref.iters, (i, r["iters"], ref.iters)
+        assert np.array_equal(r["mask"], ref.mask), i
+        rng = np.random.default_rng(100 + i)
+        pts = np.concatenate([rng.integers(0, [W, H], (2000, 2)),
+                              [[0, 0], [W - 1, H - 1]]]).astype(np.float64)
+        _, want = O.field_points(p.src, ref.scale, ref.q, ref.mask, ref.alpha, pts)
+        g = o.cpu().numpy()[pts[:, 1].astype(int), pts[:, 0].astype(int)]
+        err = float(np.abs(g - want).max())
+        worst = max(worst, err)
+        assert err <= FIELD_TOL_PX, (i, err)
+    print(f"batch of 64 ({'learned' if learned else 'plain'} start): masks and iterations "
+          f"equal, field max err {worst:.2e} px", flush=True)
+
+
+def test_benchmarked_batch64_plain_against_oracle():
+    _batch64_against_oracle(torch_or_skip(), learned=False)
+
+
+def test_benchmarked_batch64_learned_against_oracle():
+    _batch64_against_oracle(torch_or_skip(), learned=True)

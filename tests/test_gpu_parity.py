@@ -1,10 +1,9 @@
 """GPU parity: the HIP path, called through the C-ABI, against the FP64 oracle
 on the same seeded inputs.
 
-Small pairs are compared element by element over the whole output; the
-production-size pair (1280 x 1024, N = 2000, 4096^2 canvas, the launch
-configuration the benchmark times) is compared on sampled outputs the oracle
-computes one by one."""
+Every pair is compared element by element over its whole output: the small
+pairs, the production-size pair (1280 x 1024, N = 2000, 4096^2 canvas, the
+launch configuration the benchmark times) and a 1920 x 1080, N = 4000 pair."""
 import numpy as np
 import pytest
 
@@ -95,20 +94,16 @@ def test_field_kernel_alone_from_oracle_nodes():
 
 
 @pytest.mark.parametrize("pair_id", [1, 2, 3])
-def test_field_parity_production_sampled(pair_id):
+def test_field_parity_production_whole_roi(pair_id):
+    """Every one of the 1,310,720 field points of the production pair."""
     torch = torch_or_skip()
     P, ref, m, got = _fit_parity(2, pair_id, torch)
     W, H = P.cfg.width, P.cfg.height
     out = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
     m.field(0, 0, W, H, out)
-    rng = np.random.default_rng(pair_id)
-    pts = np.concatenate([rng.integers(0, [W, H], (6000, 2)),
-                          [[0, 0], [W - 1, 0], [0, H - 1], [W - 1, H - 1]]]).astype(np.float64)
-    rc, want = O.field_points(P.src, ref.scale, ref.q, ref.mask, ref.alpha, pts)
-    f = out.cpu().numpy()
-    g = f[pts[:, 1].astype(int), pts[:, 0].astype(int)]
-    err = np.abs(g - want).max()
-    print(f"production field max err {err:.2e} px over {len(pts)} samples", flush=True)
+    rc, want = O.field(P.src, ref.scale, ref.q, ref.mask, ref.alpha, 0, 0, W, H)
+    err = np.abs(out.cpu().numpy() - want).max()
+    print(f"production field max err {err:.2e} px over {W * H} points", flush=True)
     assert rc == 0 and err <= FIELD_TOL_PX
 
 
@@ -153,37 +148,63 @@ def test_warp_parity_small_whole_canvas():
     assert not got[outside].any()
 
 
+def _warp_parity_whole_roi(P, ref, m, canvas_layout, seed, torch):
+    """Warp into a canvas of random colours and weights at the layout's
+    offset; every ROI pixel against the oracle's warp of the same ROI, except
+    those whose sample point lies within 1e-3 px of the frame border; the
+    rest of the canvas must keep its bits."""
+    cw, ch, ox, oy = canvas_layout
+    W, H = P.cfg.width, P.cfg.height
+    rng = np.random.default_rng(seed)
+    init = rng.uniform(0, 255, (ch, cw, 4)).astype(np.float32)
+    init[..., 3] = rng.integers(0, 31, (ch, cw)).astype(np.float32)
+    canvas = to_dev(init, torch)
+    m.warp(to_dev(P.frame, torch), canvas, ox, oy, 0, 0, W, H)
+    got = canvas.cpu().numpy()
+    roi0 = init[oy:oy + H, ox:ox + W].astype(np.float64)
+    rc, want, valid = O.warp(P.src, ref.scale, ref.q, ref.mask, ref.alpha, P.frame, roi0,
+                             0, 0, 0, 0, W, H)
+    _, u = O.field(P.src, ref.scale, ref.q, ref.mask, ref.alpha, 0, 0, W, H)
+    keep = ~border_mask(u, W, H)
+    d = np.abs(got[oy:oy + H, ox:ox + W] - want)[keep]
+    print(f"warp {W}x{H}: max colour err {d[:, :3].max():.3e}, alpha err {d[:, 3].max()}, "
+          f"merged {int(valid.sum())}, border-excluded {int((~keep).sum())}", flush=True)
+    assert rc == 0
+    assert d[:, 3].max() == 0.0 and d[:, :3].max() <= COLOUR_TOL
+    outside = np.ones((ch, cw), bool)
+    outside[oy:oy + H, ox:ox + W] = False
+    assert np.array_equal(got[outside], init[outside])
+
+
 @pytest.mark.parametrize("pair_id", [1, 2])
-def test_warp_parity_production_sampled(pair_id):
+def test_warp_parity_production_whole_roi(pair_id):
     """1280 x 1024 frame into the 4096^2 RGBA FP32 canvas (the benchmark's
-    launch); sampled canvas pixels against the oracle."""
+    launch), every ROI pixel against the oracle."""
     torch = torch_or_skip()
     E = emdq()
     P = synth.gen_config(2, pair_id)
     ref = oracle_fit(P)
-    cw, ch, ox, oy = synth.canvas_layout(P.cfg)
-    W, H = P.cfg.width, P.cfg.height
-    rng = np.random.default_rng(10 + pair_id)
-    init = rng.uniform(0, 255, (ch, cw, 4)).astype(np.float32)
-    init[..., 3] = rng.integers(0, 31, (ch, cw)).astype(np.float32)
-    canvas = to_dev(init, torch)
     m = E.Model(P.cfg.n_matches)
     got_fit = gpu_fit(m, P, torch)
     assert np.array_equal(got_fit["mask"], ref.mask)
-    m.warp(to_dev(P.frame, torch), canvas, ox, oy, 0, 0, W, H)
-    got = canvas.cpu().numpy()
-    pts = np.concatenate([rng.integers(0, [W, H], (3000, 2)),
-                          [[0, 0], [W - 1, H - 1]]]).astype(np.float64)
-    px, py = pts[:, 0].astype(int), pts[:, 1].astype(int)
-    want, u, valid = oracle_warp_points(ref, P.src, P.frame, init[py + oy, px + ox], pts)
-    keep = ~border_mask(u, W, H)
-    g = got[py + oy, px + ox]
-    d = np.abs(g - want)[keep]
-    print(f"production warp max colour err {d[:, :3].max():.3e}, valid {valid.sum()}",
-          flush=True)
-    assert d[:, 3].max() == 0.0 and d[:, :3].max() <= COLOUR_TOL
-    # untouched pixels far from the ROI keep their bits
-    assert np.array_equal(got[:oy], init[:oy])
+    _warp_parity_whole_roi(P, ref, m, synth.canvas_layout(P.cfg), 10 + pair_id, torch)
+
+
+def test_field_and_warp_parity_fhd_whole_frame():
+    """1920 x 1080, N = 4000 in FP32: launches of 1020 32 x 64 tiles, which
+    take two 32-row blocks per wavefront.  Fit, every field point and every
+    warped pixel against the oracle."""
+    torch = torch_or_skip()
+    P, ref, m, got = _fit_parity(4, 1, torch)
+    W, H = P.cfg.width, P.cfg.height
+    out = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+    m.field(0, 0, W, H, out)
+    rc, want = O.field(P.src, ref.scale, ref.q, ref.mask, ref.alpha, 0, 0, W, H)
+    err = np.abs(out.cpu().numpy() - want).max()
+    print(f"1920x1080 field max err {err:.2e} px over {W * H} points", flush=True)
+    assert rc == 0 and err <= FIELD_TOL_PX
+    P = synth.gen_config(4, 1)
+    _warp_parity_whole_roi(P, ref, m, (W + 40, H + 24, 17, 9), 41, torch)
 
 
 def test_identity_and_similarity_invariants():
