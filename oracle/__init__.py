@@ -65,6 +65,9 @@ def lib():
                                       _D, _U8, C.POINTER(I), C.POINTER(Dd), C.POINTER(Dd)]
         L.oracle_init_features.argtypes = [I, _D, _D, Dd, _D]
         L.oracle_init_mlp.argtypes = [I, _D, _D, _D]
+        L.oracle_init_mlp_bf16.argtypes = [I, _D, _D, _D]
+        L.oracle_bf16.restype = Dd
+        L.oracle_bf16.argtypes = [Dd]
         L.oracle_start_grad.restype = Dd
         L.oracle_start_grad.argtypes = [I, _D, _D, _D, _D]
         L.oracle_field.restype = I
@@ -311,13 +314,20 @@ def init_features(src, dst, alpha_):
     return out
 
 
-def init_mlp(feat, weights):
-    """The learned start's network on features [N, 64] -> p [N]."""
+def init_mlp(feat, weights, bf16=False):
+    """The learned start's network on features [N, 64] -> p [N]; bf16: its
+    two matrix products with BF16 operands (oracle_init_mlp_bf16)."""
     feat = _d(feat)
     w = _d(weights, (N_WEIGHTS,))
     out = np.zeros(feat.shape[0])
-    lib().oracle_init_mlp(feat.shape[0], feat, w, out)
+    (lib().oracle_init_mlp_bf16 if bf16 else lib().oracle_init_mlp)(feat.shape[0], feat, w, out)
     return out
+
+
+def bf16(v) -> np.ndarray:
+    """Each value rounded to bfloat16 (nearest, ties to even), as float64."""
+    a = np.asarray(v, dtype=np.float64)
+    return np.array([lib().oracle_bf16(float(x)) for x in a.ravel()]).reshape(a.shape)
 
 
 def start_grad(feat, label, weights):

@@ -692,6 +692,50 @@ void oracle_init_mlp(int n, const double *feat, const double *w, double *p_out)
     }
 }
 
+/* bfloat16 rounding: v to the nearest number with an 8-bit significand
+ * (7 stored bits plus the implicit one) and FP32's exponent range, ties to
+ * the even significand.  Written from that definition: v = m 2^e with
+ * 0.5 <= |m| < 1, so m 2^8 is rounded to an integer, half to even (rint in
+ * the default rounding mode), and scaled back.  Zero, infinities and NaN pass
+ * through; magnitudes below FP32's normal range are not used here. */
+double oracle_bf16(double v)
+{
+    if (v == 0.0 || !isfinite(v)) return v;
+    int e;
+    const double m = frexp(v, &e);
+    return ldexp(rint(m * 256.0), e - 8);
+}
+
+/* The learned start's network with its two matrix products in BF16: the
+ * features, W1, W2 and the first hidden layer rounded to BF16 before they
+ * are multiplied; the products are exact and summed in FP64; the biases,
+ * GELU, the second hidden layer and the output layer stay in full
+ * precision.  Same weight layout as oracle_init_mlp. */
+void oracle_init_mlp_bf16(int n, const double *feat, const double *w, double *p_out)
+{
+    const double *W1 = w, *b1 = W1 + OR_NH * OR_NF, *W2 = b1 + OR_NH;
+    const double *b2 = W2 + OR_NH * OR_NH, *w3 = b2 + OR_NH, *b3 = w3 + OR_NH;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        const double *f = feat + (size_t)i * OR_NF;
+        double fb[OR_NF], h1[OR_NH], h2[OR_NH];
+        for (int k = 0; k < OR_NF; ++k) fb[k] = oracle_bf16(f[k]);
+        for (int o = 0; o < OR_NH; ++o) {
+            double a = b1[o];
+            for (int k = 0; k < OR_NF; ++k) a += oracle_bf16(W1[o * OR_NF + k]) * fb[k];
+            h1[o] = oracle_bf16(gelu(a));
+        }
+        for (int o = 0; o < OR_NH; ++o) {
+            double a = b2[o];
+            for (int k = 0; k < OR_NH; ++k) a += oracle_bf16(W2[o * OR_NH + k]) * h1[k];
+            h2[o] = gelu(a);
+        }
+        double z = b3[0];
+        for (int k = 0; k < OR_NH; ++k) z += w3[k] * h2[k];
+        p_out[i] = 1.0 / (1.0 + exp(-z));
+    }
+}
+
 /* Mean binary cross-entropy of the learned start over n labelled samples
  * (label 1 = inlier) and its gradient with respect to the flat weight vector
  * (same layout as oracle_init_mlp), by the chain rule written out layer by

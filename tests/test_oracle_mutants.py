@@ -70,6 +70,15 @@ MUTANTS = [
     ("displacement feature x and y swapped",
      "f[4 * r + 2] = ex / (1.0 + fabs(ex));\n            f[4 * r + 3] = ey / (1.0 + fabs(ey));",
      "f[4 * r + 2] = ey / (1.0 + fabs(ey));\n            f[4 * r + 3] = ex / (1.0 + fabs(ex));"),
+    ("bfloat16 ties rounded away from zero", "return ldexp(rint(m * 256.0), e - 8);",
+     "return ldexp(round(m * 256.0), e - 8);"),
+    ("bfloat16 significand one bit short", "return ldexp(rint(m * 256.0), e - 8);",
+     "return ldexp(rint(m * 128.0), e - 7);"),
+    ("first hidden layer of the BF16 network not rounded", "h1[o] = oracle_bf16(gelu(a));",
+     "h1[o] = gelu(a);"),
+    ("second weight matrix of the BF16 network not rounded",
+     "for (int k = 0; k < OR_NH; ++k) a += oracle_bf16(W2[o * OR_NH + k]) * h1[k];",
+     "for (int k = 0; k < OR_NH; ++k) a += W2[o * OR_NH + k] * h1[k];"),
 ]
 
 

@@ -666,6 +666,57 @@ def test_init_mlp_matches_torch_float64():
     assert np.allclose(got, want, rtol=1e-12, atol=1e-14)
 
 
+def test_bf16_rounding_matches_torch():
+    """The oracle's bfloat16 rounding equals torch's float32 -> bfloat16
+    conversion (nearest, ties to even) over six decades either side of 1,
+    negative values and exact ties."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(12)
+    x = (rng.standard_normal(6000) * 10.0 ** rng.integers(-6, 6, 6000)).astype(np.float32)
+    bits = (rng.integers(0, 2 ** 31, 1000).astype(np.uint32) & np.uint32(0x7FFF0000)) | \
+        np.uint32(0x8000)                       # halfway between two bfloat16 values
+    ties = bits.view(np.float32)
+    ties = ties[np.isfinite(ties) & (np.abs(ties) > 1e-30) & (np.abs(ties) < 1e30)]
+    x = np.concatenate([x, ties, -ties, [0.0, 1.0, -2.5, 1.00390625, 1.01171875]]).astype(np.float32)
+    got = O.bf16(x.astype(np.float64))
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(got, want)
+    assert O.bf16(1.00390625) == 1.0 and O.bf16(1.01171875) == 1.015625   # ties to even
+
+
+def test_init_mlp_bf16_matches_torch_float64_with_bf16_operands():
+    """The BF16 network against a float64 torch forward pass whose matrix
+    operands are rounded by torch's own bfloat16 conversion at the same
+    points (features, W1, W2, first hidden layer); the hidden layer is taken
+    to float32 first, which torch's conversion needs, and changes the
+    rounding only at values within 2^-29 of a tie."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(13)
+    w = rng.normal(0, 0.3, O.N_WEIGHTS).astype(np.float32).astype(np.float64)
+    f = rng.normal(0, 1, (60, 64)).astype(np.float32).astype(np.float64)
+    got = O.init_mlp(f, w, bf16=True)
+    full = O.init_mlp(f, w)
+    nh, nf = O.N_HIDDEN, O.N_FEAT
+    bf = lambda t: t.float().to(torch.bfloat16).double()
+    k = 0
+    def take(m):
+        nonlocal k
+        out = torch.from_numpy(w[k:k + m].copy())
+        k += m
+        return out
+    W1 = take(nh * nf).reshape(nh, nf); b1 = take(nh)
+    W2 = take(nh * nh).reshape(nh, nh); b2 = take(nh)
+    w3 = take(nh); b3 = take(1)
+    t = torch.from_numpy(f)
+    h = bf(torch.nn.functional.gelu(bf(t) @ bf(W1).T + b1))
+    h = torch.nn.functional.gelu(h @ bf(W2).T + b2)
+    want = torch.sigmoid(h @ w3 + b3).numpy()
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-14)
+    # and BF16 is a real change of the arithmetic, of the size its rounding gives
+    d = np.abs(got - full).max()
+    assert 1e-5 < d < 5e-2, d
+
+
 def test_fit_from_start_points():
     """p = 1 as an explicit start is the plain fit bit for bit; the
     generator's labels as a start reach the plain fit's mask; a non-finite
