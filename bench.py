@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--pair", type=int, default=1)
     ap.add_argument("--workload", choices=WORKLOADS, default="production")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the reports after the timed steps (learned vs plain start, "
+                         "batch forms), e.g. under a profiler")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum host time of the oracle CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -422,12 +425,12 @@ def main():
                vs_baseline=None, dtype=prec, data="synthetic",
                config=cfg, warp_only_mpix_s=round(pix / (warp_ms * 1e-3) / 1e6, 2),
                fit_ms=round(ms_per_step - warp_ms, 4), roofline=roofline, learned_init=None)
-    if wl == "production":
+    if wl == "production" and not args.no_extras:
         out["learned_init"] = learned_vs_plain(E, torch, pairs[0], stream)
         out["learned_init_fhd_n5000"] = learned_vs_plain(E, torch, synth.gen_config(5, 1),
                                                          stream)
         out["batch64"] = batch_forms(E, torch, synth.gen_batch(64), stream)
-    if batched:
+    if batched and not args.no_extras:
         out["this_form"] = dict(frames_per_s=round(len(pairs) * args.steps / wall, 2),
                                 px_err_vs_truth_rms_mean=R.truth_error())
         S = Pairs(E, torch, pairs)

@@ -365,6 +365,31 @@ emdq_status emdq_batch_prepare(emdq_batch b, int warp, int n_pairs, const emdq_m
  * prepared. */
 emdq_status emdq_batch_launch(emdq_batch b, hipStream_t stream);
 
+/* Prepares a whole batched step for emdq_batch_launch_step: the learned
+ * start of every pair (if start_weights is not null; into start_p[i],
+ * device float[n[i]]), the batched EM fit from it (else from the plain
+ * start), and the batched warp over regions[i] (as emdq_batch_warp).  The
+ * arguments mean what they mean for emdq_batch_learned_start,
+ * emdq_batch_fit and emdq_batch_warp.  The job tables are written to the
+ * batch's device memory synchronously (host-blocking); the inputs are read
+ * and the outputs written at launch time, so one preparation serves every
+ * later step on the same buffers.  EINVAL / ETOOFEW as for those calls, EHIP.
+ * Replaces the previous preparation. */
+emdq_status emdq_batch_prepare_step(emdq_batch b, int n_pairs, const emdq_model *models,
+                                    const float *const *src_xy, const float *const *dst_xy,
+                                    const int *n, const int *frame_w, const int *frame_h,
+                                    const emdq_params *params, const float *start_weights,
+                                    float *const *start_p, const emdq_region *regions);
+
+/* Enqueues the prepared step with no copy, no allocation and no host
+ * synchronisation, so the whole step can be captured in one hipGraph and
+ * replayed: the learned start (one launch), the EM of all pairs for the whole
+ * budget of params->max_iter iterations (three launches per iteration; the
+ * kernels of a pair that has stopped return at entry, so every pair's result
+ * is the bits emdq_batch_fit gives), the final fits and inlier packing, and
+ * the warp (one launch).  EINVAL if no step is prepared. */
+emdq_status emdq_batch_launch_step(emdq_batch b, hipStream_t stream);
+
 /* Waits for `stream` and returns the outcome of the last fit or
  * set_nodes: OK, WARN_NOT_CONVERGED, ENONFINITE, ENOINLIERS. */
 emdq_status emdq_model_status(emdq_model m, hipStream_t stream);

@@ -35,6 +35,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+
 #include "emdq.h"
 
 namespace {
@@ -3280,6 +3281,17 @@ struct emdq_batch_s {
     void *stage[kSlots] = {};
     hipEvent_t stage_done[kSlots] = {};
     int next_slot = 0;
+    // the prepared whole step (emdq_batch_prepare_step): device job tables
+    // and the launch shapes
+    EmJob *step_em = nullptr;
+    StartJob *step_start = nullptr;
+    FieldJob *step_field = nullptr;
+    bool step_ready = false;
+    int step_pairs = 0, step_start_wgs = 0, step_variant = 0;
+    int step_shape_blocks = 1, step_shape_n = 2;
+    long long step_blocks = 0;
+    const float *step_weights = nullptr;
+    emdq_params step_prm = {};
 };
 
 namespace {
@@ -3464,6 +3476,146 @@ int cache_lookup(const char *path, int tb, int nb) {
 
 }  // namespace
 
+// Launch shape of a batched EM: the 2D grid covers the largest pair.
+struct BatchEmShape {
+    int max_blocks = 1, max_n = 2;
+};
+
+// Validates the pairs of a batched fit and fills their job table (host
+// memory); the models record the fit's size and alpha.
+emdq_status fill_em_jobs(emdq_batch b, EmJob *jobs, int n_pairs, const emdq_model *models,
+                         const float *const *src_xy, const float *const *dst_xy, const int *n,
+                         const int *frame_w, const int *frame_h, const float *const *init_p,
+                         const emdq_params *params, BatchEmShape *shape) {
+    if (!b || !models || !src_xy || !dst_xy || !n || !frame_w || !frame_h) return EMDQ_EINVAL;
+    if (n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
+    if (!distinct_models(n_pairs, models)) return EMDQ_EINVAL;
+    emdq_params prm;
+    if (params) prm = *params; else emdq_params_default(&prm);
+    if (!params_ok(prm)) return EMDQ_EINVAL;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (!src_xy[i] || !dst_xy[i] || frame_w[i] <= 0 || frame_h[i] <= 0) return EMDQ_EINVAL;
+        if (init_p && !init_p[i]) return EMDQ_EINVAL;
+        if (n[i] < 2) return EMDQ_ETOOFEW;
+        if (n[i] > models[i]->n_max) return EMDQ_EINVAL;
+    }
+    BatchEmShape sh;
+    for (int i = 0; i < n_pairs; ++i) {
+        emdq_model m = models[i];
+        const double alpha = alpha_d(prm, frame_w[i], frame_h[i]);
+        m->n = n[i];
+        m->alpha = (float)alpha;
+        EmJob &J = jobs[i];
+        J.src = (const float2 *)src_xy[i];
+        J.dst = (const float2 *)dst_xy[i];
+        J.init_p = init_p ? init_p[i] : nullptr;
+        J.xy = m->xy;
+        J.p = m->p;
+        J.mask = m->mask;
+        J.e2 = m->e2;
+        J.part = m->part;
+        J.q = m->q;
+        J.s = m->s;
+        J.packed = m->packed;
+        J.xs = m->xs;
+        J.ys = m->ys;
+        J.st = m->st;
+        J.n = n[i];
+        J.blocks = (n[i] + kRowsPerBlock - 1) / kRowsPerBlock;
+        J.nal2 = -(float)alpha * kLog2e;
+        J.alpha = alpha;
+        J.u = 1.0 / ((double)frame_w[i] * (double)frame_h[i]);
+        if (J.blocks > sh.max_blocks) sh.max_blocks = J.blocks;
+        if (n[i] > sh.max_n) sh.max_n = n[i];
+    }
+    *shape = sh;
+    return EMDQ_OK;
+}
+
+// Enqueues the batched EM of the job table `jobs` (device).  host_stop: the
+// host reads all pairs' stop flags between chunks of iterations and stops
+// enqueuing once every pair has stopped; otherwise the whole budget of
+// max_iter iterations is enqueued with no copy and no host synchronisation
+// (the kernels of a stopped pair return at entry, so the results are the
+// same bits), which a hipGraph can capture.
+emdq_status enqueue_batch_em(emdq_batch b, const EmJob *jobs, int n_pairs,
+                             const BatchEmShape &shape, const emdq_params &prm,
+                             hipStream_t stream, bool host_stop) {
+    const unsigned P = (unsigned)n_pairs;
+    hipLaunchKernelGGL(k_reset_b, dim3(P), dim3(64), 0, stream, jobs);
+    hipLaunchKernelGGL(k_load_b, dim3((unsigned)((shape.max_n + 255) / 256), P), dim3(256), 0,
+                       stream, jobs, prm.p_thresh);
+    if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
+    auto mstep_b = [&](int final_pass) {
+        hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)shape.max_blocks, P), dim3(kEmThreads), 0,
+                           stream, jobs, final_pass);
+    };
+    int enqueued = 0;
+    for (int k = 0;; ++k) {
+        for (int c = 0; (c < kEmChunk || !host_stop) && enqueued < prm.max_iter;
+             ++c, ++enqueued) {
+            mstep_b(0);
+            hipLaunchKernelGGL(k_estep_b, dim3((unsigned)shape.max_blocks, P), dim3(kEmThreads),
+                               0, stream, jobs);
+            hipLaunchKernelGGL(k_posterior_b, dim3(P), dim3(kPostThreads), 0, stream, jobs,
+                               (double)prm.sigma2_min, (double)prm.gamma_min,
+                               (double)prm.gamma_max, prm.p_thresh, prm.max_iter);
+        }
+        if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
+        if (!host_stop) break;
+        hipLaunchKernelGGL(k_gather_states, dim3((P + 63) / 64), dim3(64), 0, stream, jobs,
+                           n_pairs, b->states + (size_t)(k & 1) * b->max_pairs);
+        if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
+        EMDQ_HIP(hipMemcpyAsync(b->host_states + (size_t)(k & 1) * b->max_pairs,
+                                b->states + (size_t)(k & 1) * b->max_pairs,
+                                sizeof(DevState) * n_pairs, hipMemcpyDeviceToHost, stream));
+        EMDQ_HIP(hipEventRecord(b->em_ev[k & 1], stream));
+        if (k > 0) {
+            EMDQ_HIP(hipEventSynchronize(b->em_ev[(k - 1) & 1]));
+            const DevState *prev = b->host_states + (size_t)((k - 1) & 1) * b->max_pairs;
+            bool all = true;
+            for (int i = 0; i < n_pairs; ++i) all = all && (prev[i].done || prev[i].status < 0);
+            if (all) break;
+        }
+        if (enqueued >= prm.max_iter) break;
+    }
+    mstep_b(1);
+    hipLaunchKernelGGL(k_compact_b, dim3(P), dim3(kCompactThreads), 0, stream, jobs);
+    return check_launch();
+}
+
+// Validates the pairs of a batched learned start and fills their job table
+// (host memory); *per receives the workgroups per pair.
+emdq_status fill_start_jobs(emdq_batch b, StartJob *jobs, int n_pairs,
+                            const float *const *src_xy, const float *const *dst_xy, const int *n,
+                            const int *frame_w, const int *frame_h, const emdq_params *params,
+                            float *const *p_out, int *per) {
+    if (!b || !src_xy || !dst_xy || !n || !frame_w || !frame_h || !p_out) return EMDQ_EINVAL;
+    if (n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
+    emdq_params prm;
+    if (params) prm = *params; else emdq_params_default(&prm);
+    if (!params_ok(prm)) return EMDQ_EINVAL;
+    int max_n = 2;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (!src_xy[i] || !dst_xy[i] || !p_out[i] || frame_w[i] <= 0 || frame_h[i] <= 0)
+            return EMDQ_EINVAL;
+        if (n[i] < 2) return EMDQ_ETOOFEW;
+        jobs[i].src = (const float2 *)src_xy[i];
+        jobs[i].dst = (const float2 *)dst_xy[i];
+        jobs[i].p_out = p_out[i];
+        jobs[i].n = n[i];
+        jobs[i].g = (float)sqrt(alpha_d(prm, frame_w[i], frame_h[i]));
+        if (n[i] > max_n) max_n = n[i];
+    }
+    // enough workgroups per pair to cover the largest one; about
+    // EMDQ_START_WGS in all
+    int wgs = (EMDQ_START_WGS + n_pairs - 1) / n_pairs;
+    const int need = (max_n + kStartWaves - 1) / kStartWaves;
+    if (wgs > need) wgs = need;
+    *per = wgs;
+    return EMDQ_OK;
+}
+
 extern "C" {
 
 emdq_status emdq_batch_create(int max_pairs, emdq_batch *out) {
@@ -3477,6 +3629,9 @@ emdq_status emdq_batch_create(int max_pairs, emdq_batch *out) {
     ok = ok && hipMalloc((void **)&b->field_jobs, n * sizeof(FieldJob)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b->start_jobs, n * sizeof(StartJob)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b->prepared, n * sizeof(FieldJob)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->step_em, n * sizeof(EmJob)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->step_start, n * sizeof(StartJob)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->step_field, n * sizeof(FieldJob)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b->states, 2 * n * sizeof(DevState)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->host_states, 2 * n * sizeof(DevState),
                              hipHostMallocDefault) == hipSuccess;
@@ -3509,6 +3664,9 @@ void emdq_batch_free(emdq_batch b) {
     (void)hipFree(b->field_jobs);
     (void)hipFree(b->start_jobs);
     (void)hipFree(b->prepared);
+    (void)hipFree(b->step_em);
+    (void)hipFree(b->step_start);
+    (void)hipFree(b->step_field);
     (void)hipFree(b->states);
     if (b->host_states) (void)hipHostFree(b->host_states);
     for (int k = 0; k < 2; ++k)
@@ -3521,91 +3679,20 @@ emdq_status emdq_batch_fit(emdq_batch b, int n_pairs, const emdq_model *models,
                            const int *n, const int *frame_w, const int *frame_h,
                            const float *const *init_p, const emdq_params *params,
                            hipStream_t stream) {
-    if (!b || !models || !src_xy || !dst_xy || !n || !frame_w || !frame_h) return EMDQ_EINVAL;
-    if (n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
-    if (!distinct_models(n_pairs, models)) return EMDQ_EINVAL;
+    if (!b) return EMDQ_EINVAL;
     emdq_params prm;
     if (params) prm = *params; else emdq_params_default(&prm);
-    if (!params_ok(prm)) return EMDQ_EINVAL;
-    for (int i = 0; i < n_pairs; ++i) {
-        if (!src_xy[i] || !dst_xy[i] || frame_w[i] <= 0 || frame_h[i] <= 0) return EMDQ_EINVAL;
-        if (init_p && !init_p[i]) return EMDQ_EINVAL;
-        if (n[i] < 2) return EMDQ_ETOOFEW;
-        if (n[i] > models[i]->n_max) return EMDQ_EINVAL;
-    }
     int slot = 0;
     EmJob *jobs = (EmJob *)batch_slot(b, &slot);
     if (!jobs) return EMDQ_EHIP;
-    int max_blocks = 1, max_n = 2;
-    for (int i = 0; i < n_pairs; ++i) {
-        emdq_model m = models[i];
-        const double alpha = alpha_d(prm, frame_w[i], frame_h[i]);
-        m->n = n[i];
-        m->alpha = (float)alpha;
-        EmJob &J = jobs[i];
-        J.src = (const float2 *)src_xy[i];
-        J.dst = (const float2 *)dst_xy[i];
-        J.init_p = init_p ? init_p[i] : nullptr;
-        J.xy = m->xy;
-        J.p = m->p;
-        J.mask = m->mask;
-        J.e2 = m->e2;
-        J.part = m->part;
-        J.q = m->q;
-        J.s = m->s;
-        J.packed = m->packed;
-        J.xs = m->xs;
-        J.ys = m->ys;
-        J.st = m->st;
-        J.n = n[i];
-        J.blocks = (n[i] + kRowsPerBlock - 1) / kRowsPerBlock;
-        J.nal2 = -(float)alpha * kLog2e;
-        J.alpha = alpha;
-        J.u = 1.0 / ((double)frame_w[i] * (double)frame_h[i]);
-        if (J.blocks > max_blocks) max_blocks = J.blocks;
-        if (n[i] > max_n) max_n = n[i];
-    }
+    BatchEmShape shape;
+    const emdq_status rc = fill_em_jobs(b, jobs, n_pairs, models, src_xy, dst_xy, n, frame_w,
+                                        frame_h, init_p, params, &shape);
+    if (rc != EMDQ_OK) return rc;
     EMDQ_HIP(hipMemcpyAsync(b->em_jobs, jobs, sizeof(EmJob) * n_pairs, hipMemcpyHostToDevice,
                             stream));
     EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
-    const unsigned P = (unsigned)n_pairs;
-    hipLaunchKernelGGL(k_reset_b, dim3(P), dim3(64), 0, stream, b->em_jobs);
-    hipLaunchKernelGGL(k_load_b, dim3((unsigned)((max_n + 255) / 256), P), dim3(256), 0, stream,
-                       b->em_jobs, prm.p_thresh);
-    if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
-    auto mstep_b = [&](int final_pass) {
-        hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0, stream,
-                           b->em_jobs, final_pass);
-    };
-    int enqueued = 0;
-    for (int k = 0;; ++k) {
-        for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
-            mstep_b(0);
-            hipLaunchKernelGGL(k_estep_b, dim3((unsigned)max_blocks, P), dim3(kEmThreads), 0,
-                               stream, b->em_jobs);
-            hipLaunchKernelGGL(k_posterior_b, dim3(P), dim3(kPostThreads), 0, stream,
-                               b->em_jobs, (double)prm.sigma2_min, (double)prm.gamma_min,
-                               (double)prm.gamma_max, prm.p_thresh, prm.max_iter);
-        }
-        hipLaunchKernelGGL(k_gather_states, dim3((P + 63) / 64), dim3(64), 0, stream,
-                           b->em_jobs, n_pairs, b->states + (size_t)(k & 1) * b->max_pairs);
-        if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
-        EMDQ_HIP(hipMemcpyAsync(b->host_states + (size_t)(k & 1) * b->max_pairs,
-                                b->states + (size_t)(k & 1) * b->max_pairs,
-                                sizeof(DevState) * n_pairs, hipMemcpyDeviceToHost, stream));
-        EMDQ_HIP(hipEventRecord(b->em_ev[k & 1], stream));
-        if (k > 0) {
-            EMDQ_HIP(hipEventSynchronize(b->em_ev[(k - 1) & 1]));
-            const DevState *prev = b->host_states + (size_t)((k - 1) & 1) * b->max_pairs;
-            bool all = true;
-            for (int i = 0; i < n_pairs; ++i) all = all && (prev[i].done || prev[i].status < 0);
-            if (all) break;
-        }
-        if (enqueued >= prm.max_iter) break;
-    }
-    mstep_b(1);
-    hipLaunchKernelGGL(k_compact_b, dim3(P), dim3(kCompactThreads), 0, stream, b->em_jobs);
-    return check_launch();
+    return enqueue_batch_em(b, b->em_jobs, n_pairs, shape, prm, stream, true);
 }
 
 emdq_status emdq_batch_learned_start(emdq_batch b, int n_pairs, const float *const *src_xy,
@@ -3613,35 +3700,17 @@ emdq_status emdq_batch_learned_start(emdq_batch b, int n_pairs, const float *con
                                      const int *frame_w, const int *frame_h,
                                      const emdq_params *params, const float *weights,
                                      float *const *p_out, hipStream_t stream) {
-    if (!b || !src_xy || !dst_xy || !n || !frame_w || !frame_h || !weights || !p_out)
-        return EMDQ_EINVAL;
-    if (n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
-    emdq_params prm;
-    if (params) prm = *params; else emdq_params_default(&prm);
-    if (!params_ok(prm)) return EMDQ_EINVAL;
+    if (!b || !weights) return EMDQ_EINVAL;
     int slot = 0;
     StartJob *jobs = (StartJob *)batch_slot(b, &slot);
     if (!jobs) return EMDQ_EHIP;
-    int max_n = 2;
-    for (int i = 0; i < n_pairs; ++i) {
-        if (!src_xy[i] || !dst_xy[i] || !p_out[i] || frame_w[i] <= 0 || frame_h[i] <= 0)
-            return EMDQ_EINVAL;
-        if (n[i] < 2) return EMDQ_ETOOFEW;
-        jobs[i].src = (const float2 *)src_xy[i];
-        jobs[i].dst = (const float2 *)dst_xy[i];
-        jobs[i].p_out = p_out[i];
-        jobs[i].n = n[i];
-        jobs[i].g = (float)sqrt(alpha_d(prm, frame_w[i], frame_h[i]));
-        if (n[i] > max_n) max_n = n[i];
-    }
+    int per = 0;
+    const emdq_status rc = fill_start_jobs(b, jobs, n_pairs, src_xy, dst_xy, n, frame_w,
+                                           frame_h, params, p_out, &per);
+    if (rc != EMDQ_OK) return rc;
     EMDQ_HIP(hipMemcpyAsync(b->start_jobs, jobs, sizeof(StartJob) * n_pairs,
                             hipMemcpyHostToDevice, stream));
     EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
-    // enough workgroups per pair to cover the largest one; about
-    // EMDQ_START_WGS in all
-    int per = (EMDQ_START_WGS + n_pairs - 1) / n_pairs;
-    const int need = (max_n + kStartWaves - 1) / kStartWaves;
-    if (per > need) per = need;
     hipLaunchKernelGGL(k_start_b, dim3((unsigned)per, (unsigned)n_pairs), dim3(kStartThreads), 0,
                        stream, b->start_jobs, weights);
     return check_launch();
@@ -3743,6 +3812,75 @@ emdq_status emdq_batch_launch(emdq_batch b, hipStream_t stream) {
     return check_launch();
 }
 
+emdq_status emdq_batch_prepare_step(emdq_batch b, int n_pairs, const emdq_model *models,
+                                    const float *const *src_xy, const float *const *dst_xy,
+                                    const int *n, const int *frame_w, const int *frame_h,
+                                    const emdq_params *params, const float *start_weights,
+                                    float *const *start_p, const emdq_region *regions) {
+    if (!b) return EMDQ_EINVAL;
+    b->step_ready = false;
+    if (start_weights && !start_p) return EMDQ_EINVAL;
+    emdq_status rc = batch_regions_ok(b, n_pairs, models, regions, kModeWarp);
+    if (rc != EMDQ_OK) return rc;
+    const size_t bytes = sizeof(EmJob) + sizeof(StartJob) + sizeof(FieldJob);
+    char *host = (char *)malloc(bytes * (size_t)n_pairs);
+    if (!host) return EMDQ_ENOMEM;
+    EmJob *em = (EmJob *)host;
+    StartJob *st = (StartJob *)(host + sizeof(EmJob) * (size_t)n_pairs);
+    FieldJob *fj = (FieldJob *)(host + (sizeof(EmJob) + sizeof(StartJob)) * (size_t)n_pairs);
+    BatchEmShape shape;
+    int wgs = 0, v = 0;
+    long long blocks = 0;
+    rc = fill_em_jobs(b, em, n_pairs, models, src_xy, dst_xy, n, frame_w, frame_h,
+                      start_weights ? (const float *const *)start_p : nullptr, params, &shape);
+    if (rc == EMDQ_OK && start_weights)
+        rc = fill_start_jobs(b, st, n_pairs, src_xy, dst_xy, n, frame_w, frame_h, params,
+                             start_p, &wgs);
+    if (rc == EMDQ_OK) {
+        v = batch_variant(b, n_pairs, regions);
+        rc = fill_field_jobs(fj, n_pairs, models, regions, kVariantSplitK[v], kVariantRows[v],
+                             &blocks);
+    }
+    if (rc == EMDQ_OK &&
+        (hipMemcpy(b->step_em, em, sizeof(EmJob) * n_pairs, hipMemcpyHostToDevice) !=
+             hipSuccess ||
+         hipMemcpy(b->step_start, st, sizeof(StartJob) * n_pairs, hipMemcpyHostToDevice) !=
+             hipSuccess ||
+         hipMemcpy(b->step_field, fj, sizeof(FieldJob) * n_pairs, hipMemcpyHostToDevice) !=
+             hipSuccess))
+        rc = EMDQ_EHIP;
+    free(host);
+    if (rc != EMDQ_OK) return rc;
+    if (params) b->step_prm = *params; else emdq_params_default(&b->step_prm);
+    b->step_pairs = n_pairs;
+    b->step_start_wgs = wgs;
+    b->step_weights = start_weights;
+    b->step_variant = v;
+    b->step_blocks = blocks;
+    b->step_shape_blocks = shape.max_blocks;
+    b->step_shape_n = shape.max_n;
+    b->step_ready = true;
+    return EMDQ_OK;
+}
+
+emdq_status emdq_batch_launch_step(emdq_batch b, hipStream_t stream) {
+    if (!b || !b->step_ready) return EMDQ_EINVAL;
+    const unsigned P = (unsigned)b->step_pairs;
+    if (b->step_weights)
+        hipLaunchKernelGGL(k_start_b, dim3((unsigned)b->step_start_wgs, P), dim3(kStartThreads),
+                           0, stream, b->step_start, b->step_weights);
+    BatchEmShape shape;
+    shape.max_blocks = b->step_shape_blocks;
+    shape.max_n = b->step_shape_n;
+    const emdq_status rc =
+        enqueue_batch_em(b, b->step_em, b->step_pairs, shape, b->step_prm, stream, false);
+    if (rc != EMDQ_OK) return rc;
+    if (b->step_blocks > 0)
+        launch_field_b(kModeWarp, b->step_variant, (unsigned)b->step_blocks, b->step_field,
+                       b->step_pairs, stream);
+    return check_launch();
+}
+
 emdq_status emdq_batch_field(emdq_batch b, int n_pairs, const emdq_model *models,
                              const emdq_region *regions, hipStream_t stream) {
     return batch_field_launch(b, n_pairs, models, regions, kModeField, stream);
@@ -3754,3 +3892,4 @@ emdq_status emdq_batch_warp(emdq_batch b, int n_pairs, const emdq_model *models,
 }
 
 }  // extern "C"
+

@@ -28,7 +28,8 @@ EXPORTS = ("emdq_params_default", "emdq_alpha", "emdq_model_create", "emdq_model
            "emdq_batch_warp", "emdq_fit_from", "emdq_learned_start",
            "emdq_batch_learned_start", "emdq_start_features", "emdq_start_train_work_floats",
            "emdq_start_train_step", "emdq_batch_autotune", "emdq_batch_set_variant",
-           "emdq_batch_prepare", "emdq_batch_launch")
+           "emdq_batch_prepare", "emdq_batch_launch", "emdq_batch_prepare_step",
+           "emdq_batch_launch_step")
 
 START_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "start_mlp.npy")
 N_START_WEIGHTS = 24961
@@ -158,6 +159,11 @@ def lib():
         L.emdq_batch_prepare.restype = I
         L.emdq_batch_launch.argtypes = [P, P]
         L.emdq_batch_launch.restype = I
+        L.emdq_batch_prepare_step.argtypes = [P, I, PP, PP, PP, IP, IP, IP, C.POINTER(Params),
+                                              P, PP, C.POINTER(Region)]
+        L.emdq_batch_prepare_step.restype = I
+        L.emdq_batch_launch_step.argtypes = [P, P]
+        L.emdq_batch_launch_step.restype = I
         L.emdq_status_string.argtypes = [I]
         L.emdq_status_string.restype = C.c_char_p
         _lib = L
@@ -597,6 +603,49 @@ class Batch:
         """The prepared launch: one kernel, capturable in a graph."""
         return _check(lib().emdq_batch_launch(self.handle, _stream(stream)),
                       "emdq_batch_launch")
+
+    def prepare_step(self, models, srcs, dsts, sizes, frames, canvases, offsets, rects,
+                     weights=None, starts=None, params=None):
+        """Job tables of a whole step for launch_step() (host-blocking): the
+        learned start into `starts` (if `weights` is given), the batched fit
+        from it (else from p = 1), and the batched warp."""
+        import torch
+        k = len(models)
+        if not (len(srcs) == len(dsts) == len(sizes) == k):
+            raise ValueError("models, srcs, dsts and sizes must have the same length")
+        if (weights is None) != (starts is None):
+            raise ValueError("weights and starts go together")
+        ps, pd, ns = [], [], []
+        for m, a, b in zip(models, srcs, dsts):
+            if a.shape != b.shape or a.dim() != 2 or a.shape[1] != 2:
+                raise ValueError("src and dst must both be [N, 2]")
+            ps.append(_dev(a, torch.float32, "src"))
+            pd.append(_dev(b, torch.float32, "dst"))
+            ns.append(int(a.shape[0]))
+            m.n = int(a.shape[0])
+        arr = lambda v, t: (t * k)(*v)
+        pw, pst = None, None
+        if weights is not None:
+            if tuple(weights.shape) != (N_START_WEIGHTS,):
+                raise ValueError("weights must be [24961]")
+            pw = _dev(weights, torch.float32, "weights")
+            for a, o in zip(srcs, starts):
+                if tuple(o.shape) != (a.shape[0],):
+                    raise ValueError("start must be [N]")
+            pst = arr([_dev(o, torch.float32, "start") for o in starts], C.c_void_p)
+        regs = self._warp_regions(models, frames, canvases, offsets, rects)
+        self._keep_step = (models, srcs, dsts, frames, canvases, weights, starts)
+        return _check(lib().emdq_batch_prepare_step(
+            self.handle, k, self._handles(models), arr(ps, C.c_void_p), arr(pd, C.c_void_p),
+            arr(ns, C.c_int), arr([w for w, _ in sizes], C.c_int),
+            arr([h for _, h in sizes], C.c_int), C.byref(params) if params is not None else None,
+            pw, pst, regs), "emdq_batch_prepare_step")
+
+    def launch_step(self, stream=None):
+        """The prepared step: no copy, no host synchronisation, capturable in
+        one graph."""
+        return _check(lib().emdq_batch_launch_step(self.handle, _stream(stream)),
+                      "emdq_batch_launch_step")
 
     def warp(self, models, frames, canvases, offsets, rects, stream=None):
         """frames: CUDA uint8 [fh, fw, 3]; canvases: CUDA float32 [ch, cw, 4];

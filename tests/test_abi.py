@@ -22,7 +22,7 @@ def test_library_exports_every_declared_function():
     from paper_2103_07414_amd import emdq as E
     L = E.lib()
     names = header_functions()
-    assert len(names) == 29
+    assert len(names) == 31
     assert sorted(E.EXPORTS) == names
     for name in names:
         assert hasattr(L, name), name
@@ -59,6 +59,9 @@ def test_host_only_calls():
     assert L.emdq_batch_set_variant(None, 0) == E.EINVAL
     assert L.emdq_batch_prepare(None, 0, 1, None, None) == E.EINVAL
     assert L.emdq_batch_launch(None, None) == E.EINVAL
+    assert L.emdq_batch_prepare_step(None, 1, None, None, None, None, None, None, None, None,
+                                     None, None) == E.EINVAL
+    assert L.emdq_batch_launch_step(None, None) == E.EINVAL
     assert L.emdq_start_features(None, None, 4, 10, 10, None, None, None) == E.EINVAL
     assert L.emdq_start_train_work_floats(0) == 0
     assert L.emdq_start_train_work_floats(3) == 4 * 24962

@@ -344,3 +344,63 @@ def test_benchmarked_batch64_plain_against_oracle():
 
 def test_benchmarked_batch64_learned_against_oracle():
     _batch64_against_oracle(torch_or_skip(), learned=True)
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_whole_step_captured_in_one_graph(learned):
+    """Learned start (or plain start) + EM + warp of a mixed batch, prepared
+    once and captured in one graph: every replay (with eager work in
+    between) gives the eager batched calls' fits and canvases bit for bit."""
+    torch = torch_or_skip()
+    E = emdq()
+    pairs = synth.gen_batch(6, seed=3031)
+    srcs = [to_dev(p.src, torch) for p in pairs]
+    dsts = [to_dev(p.dst, torch) for p in pairs]
+    frames = [to_dev(p.frame, torch) for p in pairs]
+    sizes = [(p.cfg.width, p.cfg.height) for p in pairs]
+    offs = [(3, 5)] * len(pairs)
+    rects = [(0, 0, w, h) for w, h in sizes]
+    init = [torch.full((h + 9, w + 7, 4), 2.0, dtype=torch.float32, device="cuda")
+            for w, h in sizes]
+    w = E.load_start_weights() if learned else None
+    # eager: the separate batched calls
+    me = [E.Model(p.cfg.n_matches) for p in pairs]
+    be = E.Batch(len(pairs))
+    se = [torch.empty(p.cfg.n_matches, dtype=torch.float32, device="cuda") for p in pairs]
+    if learned:
+        be.learned_start(srcs, dsts, sizes, w, se)
+    be.fit(me, srcs, dsts, sizes, init_ps=se if learned else None)
+    ce = [c.clone() for c in init]
+    be.warp(me, frames, ce, offs, rects)
+    want = [m.results() for m in me]
+    # captured whole step
+    mg = [E.Model(p.cfg.n_matches) for p in pairs]
+    bg = E.Batch(len(pairs))
+    sg = [torch.empty(p.cfg.n_matches, dtype=torch.float32, device="cuda") for p in pairs]
+    cg = [c.clone() for c in init]
+    bg.prepare_step(mg, srcs, dsts, sizes, frames, cg, offs, rects,
+                    weights=w, starts=sg if learned else None)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            bg.launch_step(stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for c, c0 in zip(cg, init):
+            c.copy_(c0)                    # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, m in enumerate(mg):
+            r = m.results()
+            for key in ("status", "iters", "n_in", "sigma2", "gamma"):
+                assert r[key] == want[i][key], (rep, i, key)
+            for key in ("p", "q", "scale", "mask"):
+                assert np.array_equal(r[key], want[i][key]), (rep, i, key)
+            assert torch.equal(cg[i], ce[i]), (rep, i)
+            if learned:
+                assert torch.equal(sg[i], se[i]), (rep, i)
+    print(f"whole step in one graph ({'learned' if learned else 'plain'} start): "
+          f"iterations {[r['iters'] for r in want]}", flush=True)
