@@ -390,6 +390,37 @@ emdq_status emdq_batch_prepare_step(emdq_batch b, int n_pairs, const emdq_model 
  * the warp (one launch).  EINVAL if no step is prepared. */
 emdq_status emdq_batch_launch_step(emdq_batch b, hipStream_t stream);
 
+/* ------------------------------------------------ allocation-free step ---
+ * For callers that cannot allocate device memory at call time (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * emdq_fit of the matches followed by emdq_warp of the fitted field, with no
+ * model object.  The model's buffers live in a library-owned static device
+ * array of about 0.7 MB per device (sized for EMDQ_STATIC_MAX_N matches), held
+ * from the first call on a device until the process ends; the call allocates
+ * nothing and never waits for the host.
+ *   src_xy, dst_xy  device float[n][2], as for emdq_fit; 2 <= n <=
+ *           EMDQ_STATIC_MAX_N
+ *   params  host pointer, null for the defaults; the frame size of the fit
+ *           (alpha scaling, outlier density) is fw x fh
+ *   frame_rgb .. h  as for emdq_warp
+ *   info    device int[3], written at the end of the step: the fit's status
+ *           (an emdq_status: OK, WARN_NOT_CONVERGED, ENONFINITE, ENOINLIERS),
+ *           the EM iterations and the number of inliers
+ * The EM runs its whole budget of params->max_iter iterations (the kernels
+ * of the iterations after the stop return at once), so the fit, its status
+ * and the canvas are bit-identical to emdq_fit + emdq_warp of the same inputs.
+ * Every call on a device shares that device's array, and each call starts by
+ * resetting the state it reads: calls that overlap on one device (two
+ * streams, two threads) race and must not be made.
+ * Returns EINVAL (null pointer, n > EMDQ_STATIC_MAX_N, or the argument rules
+ * of emdq_warp), ETOOFEW (n < 2), EHIP, or OK once the step is enqueued. */
+#define EMDQ_STATIC_MAX_N 8192
+emdq_status emdq_fit_warp_static(const float *src_xy, const float *dst_xy, int n,
+                                 const emdq_params *params, const uint8_t *frame_rgb, int fw,
+                                 int fh, int frame_pitch_bytes, float *canvas, int cw, int ch,
+                                 int canvas_pitch_px, int ox, int oy, int zx0, int zy0, int w,
+                                 int h, int *info, hipStream_t stream);
+
 /* Waits for `stream` and returns the outcome of the last fit or
  * set_nodes: OK, WARN_NOT_CONVERGED, ENONFINITE, ENOINLIERS. */
 emdq_status emdq_model_status(emdq_model m, hipStream_t stream);

@@ -35,6 +35,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 
 #include "emdq.h"
 
@@ -2755,6 +2756,19 @@ emdq_status check_launch() {
     return hipGetLastError() == hipSuccess ? EMDQ_OK : EMDQ_EHIP;
 }
 
+// The argument rules of emdq_warp (frame, canvas, target rectangle).
+bool warp_args_ok(const uint8_t *frame_rgb, int fw, int fh, int frame_pitch_bytes,
+                  const float *canvas, int cw, int ch, int canvas_pitch_px, int ox, int oy,
+                  int zx0, int zy0, int w, int h) {
+    if (!frame_rgb || !canvas) return false;
+    if (fw <= 0 || fh <= 0 || cw <= 0 || ch <= 0 || w < 0 || h < 0) return false;
+    if ((long long)frame_pitch_bytes < 3LL * fw || canvas_pitch_px < cw) return false;
+    if (((uintptr_t)canvas & 15u) != 0) return false;
+    if (w == 0 || h == 0) return true;
+    const long long cx0 = (long long)zx0 + ox, cy0 = (long long)zy0 + oy;
+    return !(cx0 < 0 || cy0 < 0 || cx0 + w > cw || cy0 + h > ch);
+}
+
 bool params_ok(const emdq_params &p) {
     return p.alpha0 > 0.f && p.ref_w > 0 && p.ref_h > 0 && p.max_iter >= 1 &&
            p.max_iter <= 100000 && p.p_thresh > 0.f && p.p_thresh < 1.f &&
@@ -2767,9 +2781,12 @@ double alpha_d(const emdq_params &p, int w, int h) {
     return (double)p.alpha0 / (s * s);
 }
 
+// host_sync = false: the EM's whole budget of max_iter iterations is
+// enqueued without reading a stop flag (the kernels after the stop return at
+// entry, so the bits are those of the host-synchronised fit).
 emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int n,
                      int frame_w, int frame_h, const emdq_params *params, const float *init_p,
-                     hipStream_t stream);
+                     hipStream_t stream, bool host_sync = true);
 
 emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h, float2 *out,
                          const uint8_t *frame, int fw, int fh, int fpitch, float4 *canvas,
@@ -2969,7 +2986,7 @@ namespace {
 
 emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int n,
                      int frame_w, int frame_h, const emdq_params *params, const float *init_p,
-                     hipStream_t stream) {
+                     hipStream_t stream, bool host_sync) {
     if (!m || !src_xy || !dst_xy) return EMDQ_EINVAL;
     emdq_params prm;
     if (params) prm = *params; else emdq_params_default(&prm);
@@ -3023,7 +3040,7 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
         // the loop leaves once max_iter iterations are enqueued)
         for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
             const bool last = c + 1 == kEmChunk || enqueued + 1 == prm.max_iter;
-            DevState *slot = last ? &m->em_st_dev[k & 1] : nullptr;
+            DevState *slot = last && host_sync ? &m->em_st_dev[k & 1] : nullptr;
             const int it = enqueued + 1;
             mstep(it, 0);
             if (fused) {
@@ -3038,6 +3055,10 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
             }
         }
         if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
+        if (!host_sync) {
+            if (enqueued >= prm.max_iter) break;
+            continue;
+        }
         EMDQ_HIP(hipEventRecord(m->em_ev[k & 1], stream));
         if (k > 0) {
             EMDQ_HIP(hipEventSynchronize(m->em_ev[(k - 1) & 1]));
@@ -3116,13 +3137,11 @@ emdq_status emdq_warp(emdq_model m, const uint8_t *frame_rgb, int fw, int fh,
                       int frame_pitch_bytes, float *canvas, int cw, int ch,
                       int canvas_pitch_px, int ox, int oy, int zx0, int zy0, int w, int h,
                       hipStream_t stream) {
-    if (!m || !frame_rgb || !canvas) return EMDQ_EINVAL;
-    if (fw <= 0 || fh <= 0 || cw <= 0 || ch <= 0 || w < 0 || h < 0) return EMDQ_EINVAL;
-    if ((long long)frame_pitch_bytes < 3LL * fw || canvas_pitch_px < cw) return EMDQ_EINVAL;
-    if (((uintptr_t)canvas & 15u) != 0) return EMDQ_EINVAL;
+    if (!m) return EMDQ_EINVAL;
+    if (!warp_args_ok(frame_rgb, fw, fh, frame_pitch_bytes, canvas, cw, ch, canvas_pitch_px, ox,
+                      oy, zx0, zy0, w, h))
+        return EMDQ_EINVAL;
     if (w == 0 || h == 0) return EMDQ_OK;
-    const long long cx0 = (long long)zx0 + ox, cy0 = (long long)zy0 + oy;
-    if (cx0 < 0 || cy0 < 0 || cx0 + w > cw || cy0 + h > ch) return EMDQ_EINVAL;
     return launch_field(m, kModeWarp, zx0, zy0, w, h, nullptr, frame_rgb, fw, fh,
                         frame_pitch_bytes, (float4 *)canvas, canvas_pitch_px, ox, oy, stream);
 }
@@ -3893,3 +3912,117 @@ emdq_status emdq_batch_warp(emdq_batch b, int n_pairs, const emdq_model *models,
 
 }  // extern "C"
 
+
+// ---------------------------------------------------- allocation-free entry ----
+//
+// emdq_fit_warp_static: emdq_fit followed by emdq_warp, with every device
+// buffer of the model carved from one file-scope device array, so that the
+// call allocates nothing.  Each device the library runs on holds its own copy
+// of the array; its address is taken with hipGetSymbolAddress once per device
+// (the array's name in host code is only a stand-in) and handed to the
+// kernels like any model buffer.
+
+namespace {
+
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kStN = EMDQ_STATIC_MAX_N;
+constexpr size_t kStNb = (kStN + kRowsPerBlock - 1) / kRowsPerBlock;
+// byte offsets of the model's buffers in the array
+constexpr size_t kStXy = 0;
+constexpr size_t kStP = kStXy + round256(kStN * sizeof(float4));
+constexpr size_t kStMask = kStP + round256(kStN * sizeof(float));
+constexpr size_t kStE2 = kStMask + round256(kStN);
+constexpr size_t kStPart = kStE2 + round256(kStN * sizeof(float));
+constexpr size_t kStChg = kStPart + round256(kStNb * sizeof(double2));
+constexpr size_t kStQ = kStChg + round256(kStNb * sizeof(int));
+constexpr size_t kStS = kStQ + round256(kStN * sizeof(float4));
+constexpr size_t kStPacked = kStS + round256(kStN * sizeof(float));
+constexpr size_t kStXs = kStPacked + round256(2 * kStN * sizeof(float4));
+constexpr size_t kStYs = kStXs + round256((kStN + kHK) * sizeof(float));
+constexpr size_t kStSt = kStYs + round256((kStN + kHK) * sizeof(float));
+constexpr size_t kStBytes = kStSt + round256(sizeof(DevState));
+static_assert(kStBytes < (1u << 20), "the static scratch stays under 1 MiB");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStBytes];
+
+namespace {
+
+constexpr int kStMaxDevices = 64;
+std::mutex g_st_mu;
+bool g_st_ready[kStMaxDevices];
+emdq_model_s g_st_model[kStMaxDevices];   // host records; their pointers address `scratch`
+
+// The model of the current device whose buffers live in `scratch`, set up on
+// the first call on that device.
+emdq_status static_model(emdq_model *out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return EMDQ_EHIP;
+    if (dev < 0 || dev >= kStMaxDevices) return EMDQ_EINVAL;
+    std::lock_guard<std::mutex> lock(g_st_mu);
+    if (!g_st_ready[dev]) {
+        unsigned char *ptr = nullptr;
+        if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return EMDQ_EHIP;
+        emdq_model_s &m = g_st_model[dev];
+        m.n_max = (int)kStN;
+        m.device = dev;
+        m.xy = (float4 *)(ptr + kStXy);
+        m.p = (float *)(ptr + kStP);
+        m.mask = ptr + kStMask;
+        m.e2 = (float *)(ptr + kStE2);
+        m.part = (double2 *)(ptr + kStPart);
+        m.chg = (int *)(ptr + kStChg);
+        m.q = (float4 *)(ptr + kStQ);
+        m.s = (float *)(ptr + kStS);
+        m.packed = (float4 *)(ptr + kStPacked);
+        m.xs = (float *)(ptr + kStXs);
+        m.ys = (float *)(ptr + kStYs);
+        m.st = (DevState *)(ptr + kStSt);
+        g_st_ready[dev] = true;
+    }
+    *out = &g_st_model[dev];
+    return EMDQ_OK;
+}
+
+__global__ void k_export_state(const DevState *__restrict__ st, int *__restrict__ info) {
+    if (threadIdx.x == 0) {
+        info[0] = st->status;
+        info[1] = st->iter;
+        info[2] = st->n_in;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+emdq_status emdq_fit_warp_static(const float *src_xy, const float *dst_xy, int n,
+                                 const emdq_params *params, const uint8_t *frame_rgb, int fw,
+                                 int fh, int frame_pitch_bytes, float *canvas, int cw, int ch,
+                                 int canvas_pitch_px, int ox, int oy, int zx0, int zy0, int w,
+                                 int h, int *info, hipStream_t stream) {
+    if (!src_xy || !dst_xy || !info) return EMDQ_EINVAL;
+    if (!warp_args_ok(frame_rgb, fw, fh, frame_pitch_bytes, canvas, cw, ch, canvas_pitch_px, ox,
+                      oy, zx0, zy0, w, h))
+        return EMDQ_EINVAL;
+    if (n < 2) return EMDQ_ETOOFEW;
+    if (n > EMDQ_STATIC_MAX_N) return EMDQ_EINVAL;
+    emdq_model m = nullptr;
+    const emdq_status rc = static_model(&m);
+    if (rc != EMDQ_OK) return rc;
+    const emdq_status fr = fit_impl(m, src_xy, dst_xy, n, fw, fh, params, nullptr, stream,
+                                    /*host_sync=*/false);
+    if (fr != EMDQ_OK) return fr;
+    if (w > 0 && h > 0) {
+        const emdq_status wr = launch_field(m, kModeWarp, zx0, zy0, w, h, nullptr, frame_rgb, fw,
+                                            fh, frame_pitch_bytes, (float4 *)canvas,
+                                            canvas_pitch_px, ox, oy, stream);
+        if (wr != EMDQ_OK) return wr;
+    }
+    hipLaunchKernelGGL(k_export_state, dim3(1), dim3(64), 0, stream, m->st, info);
+    return check_launch();
+}
+
+}  // extern "C"

@@ -29,7 +29,9 @@ EXPORTS = ("emdq_params_default", "emdq_alpha", "emdq_model_create", "emdq_model
            "emdq_batch_learned_start", "emdq_start_features", "emdq_start_train_work_floats",
            "emdq_start_train_step", "emdq_batch_autotune", "emdq_batch_set_variant",
            "emdq_batch_prepare", "emdq_batch_launch", "emdq_batch_prepare_step",
-           "emdq_batch_launch_step")
+           "emdq_batch_launch_step", "emdq_fit_warp_static")
+
+STATIC_MAX_N = 8192   # EMDQ_STATIC_MAX_N
 
 START_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "start_mlp.npy")
 N_START_WEIGHTS = 24961
@@ -164,6 +166,9 @@ def lib():
         L.emdq_batch_prepare_step.restype = I
         L.emdq_batch_launch_step.argtypes = [P, P]
         L.emdq_batch_launch_step.restype = I
+        L.emdq_fit_warp_static.argtypes = [P, P, I, C.POINTER(Params), U8P, I, I, I, P, I, I,
+                                           I, I, I, I, I, I, I, P, P]
+        L.emdq_fit_warp_static.restype = I
         L.emdq_status_string.argtypes = [I]
         L.emdq_status_string.restype = C.c_char_p
         _lib = L
@@ -358,6 +363,30 @@ def emdq_warp(model: int, frame, canvas, ox: int, oy: int, zx0: int, zy0: int, w
     ch, cw = int(canvas.shape[0]), int(canvas.shape[1])
     return _check(lib().emdq_warp(model, pf, fw, fh, 3 * fw, pc, cw, ch, cw, ox, oy, zx0, zy0,
                                   w, h, _stream(stream)), "emdq_warp")
+
+
+def emdq_fit_warp_static(src, dst, frame, canvas, ox: int, oy: int, zx0: int, zy0: int, w: int,
+                         h: int, info, params: Params | None = None, stream=None) -> int:
+    """Allocation-free fit + warp: src, dst CUDA float32 [N, 2]; frame CUDA
+    uint8 [fh, fw, 3]; canvas CUDA float32 [ch, cw, 4] (updated); info CUDA
+    int32 [3] (status, EM iterations, inliers, written on the stream)."""
+    import torch
+    if src.shape != dst.shape or src.dim() != 2 or src.shape[1] != 2:
+        raise ValueError("src and dst must both be [N, 2]")
+    if frame.dim() != 3 or frame.shape[2] != 3:
+        raise ValueError("frame must be [fh, fw, 3]")
+    if canvas.dim() != 3 or canvas.shape[2] != 4:
+        raise ValueError("canvas must be [ch, cw, 4]")
+    if tuple(info.shape) != (3,):
+        raise ValueError("info must be [3]")
+    fh, fw = int(frame.shape[0]), int(frame.shape[1])
+    ch, cw = int(canvas.shape[0]), int(canvas.shape[1])
+    return _check(lib().emdq_fit_warp_static(
+        _dev(src, torch.float32, "src"), _dev(dst, torch.float32, "dst"), int(src.shape[0]),
+        C.byref(params) if params is not None else None, _dev(frame, torch.uint8, "frame"),
+        fw, fh, 3 * fw, _dev(canvas, torch.float32, "canvas"), cw, ch, cw, int(ox), int(oy),
+        int(zx0), int(zy0), int(w), int(h), _dev(info, torch.int32, "info"), _stream(stream)),
+        "emdq_fit_warp_static")
 
 
 def emdq_uncertainty(model: int, beta: float, zx0: int, zy0: int, w: int, h: int, out,
