@@ -1123,15 +1123,32 @@ __device__ __forceinline__ void warp_merge_batch(const int (&zx)[NB], const int 
     }
 }
 
+// One per-axis Gaussian factor exp(-alpha d^2) = 2^(nal2 d^2), nal2 =
+// -alpha log2(e), d = z - x_j along one axis.  The in-loop blend and the
+// factor tables both call this, so both give the same bits.
+__device__ __forceinline__ float axis_factor(float nal2, float d) {
+    return fast_exp2(nal2 * d * d);
+}
+
+// Per-launch factor tables of the FP32 blend, inlier-major: gx[j * sx + c] =
+// axis_factor(nal2, zx0 + c - x_j) for the region's columns c, gy[j * sy + r]
+// likewise for its rows r (sx, sy: the region's width and height rounded up
+// to whole tiles).  Null gx: the factors are computed in the blend's loop.
+struct FieldTabs {
+    const float *gx, *gy;
+    int sx, sy;
+};
+
 // RB row blocks of 32 share the B operands: a wavefront's tile is 32 RB rows x
 // 32 columns and each pair of inliers costs RB + 1 exponentials and 6
-// multiplies for 6 RB MFMAs.
-template <int MODE, int SPLITK, int RB>
+// multiplies for 6 RB MFMAs; with factor tables (TAB), RB + 1 table loads
+// and 5 multiplies (the weight column is the x factor itself).
+template <int MODE, int SPLITK, int RB, bool TAB = false>
 __device__ __forceinline__ void field_body(
     const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
     int zy0, int w, int h, int tiles_x, int n_tiles, float2 *__restrict__ out,
     const uint8_t *__restrict__ frame, int fw, int fh, int fpitch, float4 *__restrict__ canvas,
-    int cpitch, int ox, int oy, int block) {
+    int cpitch, int ox, int oy, int block, FieldTabs tabs = FieldTabs{}) {
     constexpr int kTilesPerWg = 4 / SPLITK;
     constexpr int kRegsOwned = 16 / SPLITK;
     __shared__ FieldLds<SPLITK, RB> lds;
@@ -1173,12 +1190,8 @@ __device__ __forceinline__ void field_body(
         const int voff = half * 32;        // lanes 32..63 take the odd inlier
         auto factors = [&](const float4 &r0, float (&a)[RB], float &g) {
 #pragma unroll
-            for (int b = 0; b < RB; ++b) {
-                const float dy = zrow[b] - r0.y;
-                a[b] = fast_exp2(nal2 * dy * dy);
-            }
-            const float dx = zcol - r0.x;
-            g = fast_exp2(nal2 * dx * dx);
+            for (int b = 0; b < RB; ++b) a[b] = axis_factor(nal2, zrow[b] - r0.y);
+            g = axis_factor(nal2, zcol - r0.x);
         };
         auto load = [&](int j0, float4 &r0, float4 &r1) {
             const int jj = __builtin_amdgcn_readfirstlane(min(j0, n_in));
@@ -1189,6 +1202,60 @@ __device__ __forceinline__ void field_body(
             r1 = __builtin_bit_cast(float4,
                                     __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16, 0, 0));
         };
+        if constexpr (TAB) {
+            // Factor tables: the A operands (rows) and the B factor (column)
+            // of the lane's inlier j + half are table loads, 128 contiguous
+            // bytes per half-wavefront; rows at or past n_in read as zero
+            // (buffer range check), and so add nothing.  Same ring as below.
+            const int lx = tx * kTile + col, ly = ty * kTile * RB + col;
+            auto tload = [&](int j0, float4 &r0, float4 &r1, float (&ta)[RB], float &tg) {
+                load(j0, r0, r1);
+                const int jj = __builtin_amdgcn_readfirstlane(min(j0, n_in));
+                const int rows = __builtin_amdgcn_readfirstlane(n_in - jj);
+                const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(tabs.gx + (size_t)jj * tabs.sx), (short)0, rows * tabs.sx * 4,
+                    kBufferFlags);
+                const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(tabs.gy + (size_t)jj * tabs.sy), (short)0, rows * tabs.sy * 4,
+                    kBufferFlags);
+                tg = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                   rx, (half * tabs.sx + lx) * 4, 0, 0));
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    ta[b] = __builtin_bit_cast(
+                        float, __builtin_amdgcn_raw_buffer_load_b32(
+                                   ry, (half * tabs.sy + ly + kTile * b) * 4, 0, 0));
+            };
+            float4 ra[kRing], rb[kRing];
+            float ta[kRing][RB], tg[kRing];
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) {
+                tload(kb + 2 * u, ra[u], rb[u], ta[u], tg[u]);
+                __builtin_amdgcn_sched_barrier(0);   // issue in ring order
+            }
+            for (int j0 = kb; j0 < kend; j0 += 2 * kRing) {
+#pragma unroll
+                for (int u = 0; u < kRing; ++u) {
+                    const int j = j0 + 2 * u;
+                    const float4 r0 = ra[u], r1 = rb[u];
+                    const float q[5] = {r0.z, r0.w, r1.x, r1.y, r1.z};
+                    float a[RB];
+#pragma unroll
+                    for (int bl = 0; bl < RB; ++bl) a[bl] = ta[u][bl];
+                    const float g = tg[u];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        const float bop = c < 5 ? g * q[c] : g;
+#pragma unroll
+                        for (int bl = 0; bl < RB; ++bl)
+                            acc[bl][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bl], bop,
+                                                                              acc[bl][c], 0, 0, 0);
+                    }
+                    tload(j + 2 * kRing, ra[u], rb[u], ta[u], tg[u]);
+                    __builtin_amdgcn_sched_barrier(EMDQ_SCHED_MASK);
+                }
+            }
+        } else {
         // Ring of kRing record buffers: step u of a group uses buffer u and
         // refills it for the same step of the next group, so every load has
         // kRing K steps to land.  The Gaussian factors of step u + 1 are
@@ -1227,6 +1294,7 @@ __device__ __forceinline__ void field_body(
                 __builtin_amdgcn_sched_barrier(EMDQ_SCHED_MASK);
             }
         }
+        }   // TAB
     }
 
     // ---- split-K reduction, then the epilogue, specialised per wavefront of
@@ -1335,14 +1403,62 @@ __device__ __forceinline__ void field_body(
     }
 }
 
-template <int MODE, int SPLITK, int RB>
+template <int MODE, int SPLITK, int RB, bool TAB>
 __global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(field_waves(RB), field_waves(RB)))) void k_field(
     const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
     int zy0, int w, int h, int tiles_x, int n_tiles, float2 *__restrict__ out,
     const uint8_t *__restrict__ frame, int fw, int fh, int fpitch, float4 *__restrict__ canvas,
-    int cpitch, int ox, int oy) {
-    field_body<MODE, SPLITK, RB>(packed, st, nal2, zx0, zy0, w, h, tiles_x, n_tiles, out, frame, fw, fh, fpitch, canvas, cpitch, ox, oy, blockIdx.x);
+    int cpitch, int ox, int oy, FieldTabs tabs) {
+    field_body<MODE, SPLITK, RB, TAB>(packed, st, nal2, zx0, zy0, w, h, tiles_x, n_tiles, out,
+                                      frame, fw, fh, fpitch, canvas, cpitch, ox, oy, blockIdx.x,
+                                      tabs);
 }
+
+// The factor tables of an FP32 blend over a region (FieldTabs): row j of
+// each table belongs to inlier j; a thread owns four consecutive entries of
+// the rows (x entries first, then y) and writes them for kTabRowsPerThread
+// consecutive rows, whose coordinates it loads first, all at once.  Rows
+// j >= n_in are not written (the blend reads them as zero).  Grid: x over the
+// ceil((sx + sy) / 4) entry groups of a row, y over blocks of rows.
+constexpr int kTabThreads = 256;
+constexpr int kTabRowsPerThread = 8;
+
+// Four consecutive entries z0 .. z0 + 3 of rows 0 .. min(nrows, 8) - 1 (row r
+// at dst + r * stride, coordinate xj[r]).
+__device__ __forceinline__ void table_rows(const float (&xj)[kTabRowsPerThread], int nrows,
+                                           float nal2, float z0, float *dst, int stride) {
+    const float z1 = z0 + 1.f, z2 = z0 + 2.f, z3 = z0 + 3.f;
+#pragma unroll
+    for (int r = 0; r < kTabRowsPerThread; ++r) {
+        if (r >= nrows) break;
+        float4 v;
+        v.x = axis_factor(nal2, z0 - xj[r]);
+        v.y = axis_factor(nal2, z1 - xj[r]);
+        v.z = axis_factor(nal2, z2 - xj[r]);
+        v.w = axis_factor(nal2, z3 - xj[r]);
+        *(float4 *)(dst + (size_t)r * stride) = v;
+    }
+}
+__global__ __launch_bounds__(kTabThreads) void k_field_tables(
+    const float *__restrict__ xs, const float *__restrict__ ys,
+    const DevState *__restrict__ st, float nal2, int zx0, int zy0, float *__restrict__ gx,
+    float *__restrict__ gy, int sx, int sy) {
+    const int n_in = st->status < 0 ? 0 : st->n_in;
+    const int j0 = kTabRowsPerThread * (int)blockIdx.y;
+    const int e = 4 * (int)(blockIdx.x * kTabThreads + threadIdx.x);
+    if (j0 >= n_in || e >= sx + sy) return;
+    const bool is_x = e < sx;   // sx is a multiple of 4: a group never straddles
+    const float *src = is_x ? xs : ys;
+    const int c0 = is_x ? e : e - sx;
+    const int stride = is_x ? sx : sy;
+    float *dst = (is_x ? gx : gy) + c0;
+    float xj[kTabRowsPerThread];
+#pragma unroll
+    for (int r = 0; r < kTabRowsPerThread; ++r) xj[r] = src[min(j0 + r, n_in - 1)];
+    table_rows(xj, n_in - j0, nal2, (float)((is_x ? zx0 : zy0) + c0), dst + (size_t)j0 * stride,
+               stride);
+}
+
 
 
 // ------------------------------------------- half-precision field / warp ----
@@ -2609,6 +2725,13 @@ constexpr int kSplitK = EMDQ_SPLITK;
 #define EMDQ_RB2_MIN_TILES 768
 #endif
 constexpr long long kRb2MinTiles = EMDQ_RB2_MIN_TILES;
+// FP32 blend: factor tables (per model, kF32TabCols floats per match) for
+// regions whose padded width + height fit; larger regions compute the
+// factors in the loop.
+#ifndef EMDQ_F32_TABLES
+#define EMDQ_F32_TABLES 1
+#endif
+constexpr long long kF32TabCols = 4096;
 
 inline long long tiles64(int w, int h) {
     return (long long)((w + kTile - 1) / kTile) * ((h + 2 * kTile - 1) / (2 * kTile));
@@ -2643,6 +2766,8 @@ struct EmJob {
 
 struct FieldJob {
     const float4 *packed;
+    const float *xs, *ys;   // the inlier coordinates (factor tables)
+    FieldTabs tabs;         // factor tables of this pair (none: in-loop factors)
     const DevState *st;
     float2 *out;
     const uint8_t *frame;
@@ -2700,7 +2825,7 @@ __global__ void k_gather_states(const EmJob *__restrict__ jobs, int n_pairs,
     if (i < n_pairs) out[i] = *jobs[i].st;
 }
 
-template <int MODE, int SPLITK, int RB>
+template <int MODE, int SPLITK, int RB, bool TAB>
 __global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(field_waves(RB), field_waves(RB)))) void k_field_b(const FieldJob *__restrict__ jobs,
                                                            int n_jobs) {
     int lo = 0, hi = n_jobs - 1;   // last job whose first workgroup is <= blockIdx.x
@@ -2709,10 +2834,37 @@ __global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(f
         if (jobs[mid].block_base <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
     }
     const FieldJob &J = jobs[lo];
-    field_body<MODE, SPLITK, RB>(J.packed, J.st, J.nal2, J.zx0, J.zy0, J.w, J.h,
-                                          J.tiles_x, J.n_tiles, J.out, J.frame, J.fw, J.fh,
-                                          J.fpitch, J.canvas, J.cpitch, J.ox, J.oy,
-                                          (int)blockIdx.x - J.block_base);
+    field_body<MODE, SPLITK, RB, TAB>(J.packed, J.st, J.nal2, J.zx0, J.zy0, J.w, J.h,
+                                      J.tiles_x, J.n_tiles, J.out, J.frame, J.fw, J.fh,
+                                      J.fpitch, J.canvas, J.cpitch, J.ox, J.oy,
+                                      (int)blockIdx.x - J.block_base, J.tabs);
+}
+
+// Batched factor tables: workgroup (blockIdx.x, blockIdx.y) writes rows
+// [kTabRowsPerThread blockIdx.x, +kTabRowsPerThread) of pair blockIdx.y's
+// tables (FieldJob::tabs; none: nothing to do), its threads striding over the
+// entry groups of those rows.
+__global__ __launch_bounds__(kTabThreads) void k_field_tables_b(const FieldJob *__restrict__ jobs) {
+    const FieldJob &J = jobs[blockIdx.y];
+    if (!J.tabs.gx) return;
+    const int n_in = J.st->status < 0 ? 0 : J.st->n_in;
+    const int j0 = kTabRowsPerThread * (int)blockIdx.x;
+    if (j0 >= n_in) return;
+    const int sx = J.tabs.sx, sy = J.tabs.sy;
+    float xr[kTabRowsPerThread], yr[kTabRowsPerThread];
+#pragma unroll
+    for (int r = 0; r < kTabRowsPerThread; ++r) {
+        xr[r] = J.xs[min(j0 + r, n_in - 1)];
+        yr[r] = J.ys[min(j0 + r, n_in - 1)];
+    }
+    for (int e = 4 * (int)threadIdx.x; e < sx + sy; e += 4 * kTabThreads) {
+        if (e < sx)
+            table_rows(xr, n_in - j0, J.nal2, (float)(J.zx0 + e),
+                       (float *)J.tabs.gx + (size_t)j0 * sx + e, sx);
+        else
+            table_rows(yr, n_in - j0, J.nal2, (float)(J.zy0 + e - sx),
+                       (float *)J.tabs.gy + (size_t)j0 * sy + (e - sx), sy);
+    }
 }
 
 }  // namespace
@@ -2737,6 +2889,7 @@ struct emdq_model_s {
     float *ys = nullptr;
     int precision = EMDQ_PREC_F32;
     void *half_tab = nullptr;   // x and y factor tables of the half-precision blend
+    float *f32_tab = nullptr;   // factor tables of the FP32 blend: n_max x kF32TabCols
     int tab_stride = 0;         // values per table row: n_max rounded up to 64
     DevState *st = nullptr;
     DevState *host_st = nullptr;   // pinned
@@ -2843,17 +2996,38 @@ emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h,
         return check_launch();
     }
     const float nal2 = -m->alpha * kLog2e;
-#define EMDQ_F(M, R, O, F, C)                                                                \
-    hipLaunchKernelGGL((k_field<M, kSplitK, R>), dim3((unsigned)blocks), dim3(kFieldThreads), \
-                       0, stream, m->packed, m->st, nal2, zx0, zy0, w, h, tiles_x,           \
-                       (int)n_tiles, O, F, fw, fh, fpitch, C, cpitch, ox, oy)
-    if (mode == kModeField) {
-        if (rb == 2) EMDQ_F(kModeField, 2, out, nullptr, nullptr);
-        else EMDQ_F(kModeField, 1, out, nullptr, nullptr);
-    } else {
-        if (rb == 2) EMDQ_F(kModeWarp, 2, nullptr, frame, canvas);
-        else EMDQ_F(kModeWarp, 1, nullptr, frame, canvas);
+    // factor tables when the region's padded rows fit the model's table
+    // (same bits either way)
+    FieldTabs tabs{};
+    const long long sxp = (long long)tiles_x * kTile, syp = (long long)tiles_y * kTile * rb;
+    if (m->f32_tab && m->n > 0 && sxp + syp <= kF32TabCols) {
+        tabs.gx = m->f32_tab;
+        tabs.gy = m->f32_tab + (size_t)m->n_max * sxp;
+        tabs.sx = (int)sxp;
+        tabs.sy = (int)syp;
+        const unsigned gxb = (unsigned)((sxp + syp + 4 * kTabThreads - 1) / (4 * kTabThreads));
+        const unsigned gyb = (unsigned)((m->n + kTabRowsPerThread - 1) / kTabRowsPerThread);
+        hipLaunchKernelGGL(k_field_tables, dim3(gxb, gyb), dim3(kTabThreads), 0,
+                           stream, m->xs, m->ys, m->st, nal2, zx0, zy0, (float *)tabs.gx,
+                           (float *)tabs.gy, tabs.sx, tabs.sy);
     }
+#define EMDQ_F(M, R, T, O, F, C)                                                                \
+    hipLaunchKernelGGL((k_field<M, kSplitK, R, T>), dim3((unsigned)blocks),                  \
+                       dim3(kFieldThreads), 0, stream, m->packed, m->st, nal2, zx0, zy0, w, h, \
+                       tiles_x, (int)n_tiles, O, F, fw, fh, fpitch, C, cpitch, ox, oy, tabs)
+#define EMDQ_FT(M, R, O, F, C)                 \
+    do {                                       \
+        if (tabs.gx) EMDQ_F(M, R, true, O, F, C); \
+        else EMDQ_F(M, R, false, O, F, C);        \
+    } while (0)
+    if (mode == kModeField) {
+        if (rb == 2) EMDQ_FT(kModeField, 2, out, nullptr, nullptr);
+        else EMDQ_FT(kModeField, 1, out, nullptr, nullptr);
+    } else {
+        if (rb == 2) EMDQ_FT(kModeWarp, 2, nullptr, frame, canvas);
+        else EMDQ_FT(kModeWarp, 1, nullptr, frame, canvas);
+    }
+#undef EMDQ_FT
 #undef EMDQ_F
     return check_launch();
 }
@@ -2920,6 +3094,8 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     ok = ok && hipMalloc((void **)&m->xs, (n + kHK) * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->ys, (n + kHK) * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->st, sizeof(DevState)) == hipSuccess;
+    if (ok && EMDQ_F32_TABLES && n_max <= 65535)
+        ok = hipMalloc((void **)&m->f32_tab, n * kF32TabCols * sizeof(float)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&m->host_st, sizeof(DevState), hipHostMallocDefault) ==
                    hipSuccess;
     // coherent: the EM's E-step or posterior kernel stores the stop flags
@@ -2966,6 +3142,7 @@ void emdq_model_free(emdq_model m) {
     (void)hipFree(m->xs);
     (void)hipFree(m->ys);
     (void)hipFree(m->half_tab);
+    (void)hipFree(m->f32_tab);
     (void)hipFree(m->st);
     if (m->host_st) (void)hipHostFree(m->host_st);
     if (m->em_st) (void)hipHostFree(m->em_st);
@@ -3291,7 +3468,7 @@ struct emdq_batch_s {
     StartJob *start_jobs = nullptr;  // device
     FieldJob *prepared = nullptr;    // device: the table of emdq_batch_prepare
     int variant = -1;                // field-kernel shape (autotuner); -1: by size
-    int prep_mode = -1, prep_pairs = 0, prep_variant = 0;
+    int prep_mode = -1, prep_pairs = 0, prep_variant = 0, prep_tab_rows = 0;
     long long prep_blocks = 0;
     DevState *states = nullptr;      // device, gathered per chunk
     DevState *host_states = nullptr; // pinned, two sets (read while the EM runs on)
@@ -3306,7 +3483,7 @@ struct emdq_batch_s {
     StartJob *step_start = nullptr;
     FieldJob *step_field = nullptr;
     bool step_ready = false;
-    int step_pairs = 0, step_start_wgs = 0, step_variant = 0;
+    int step_pairs = 0, step_start_wgs = 0, step_variant = 0, step_tab_rows = 0;
     int step_shape_blocks = 1, step_shape_n = 2;
     long long step_blocks = 0;
     const float *step_weights = nullptr;
@@ -3364,7 +3541,8 @@ constexpr int kVariantRows[kBatchVariants] = {1, 1, 1, 2};   // 32-row blocks pe
 // count (largest first), so the most expensive tiles are dispatched first.
 emdq_status fill_field_jobs(FieldJob *jobs, int n_pairs, const emdq_model *models,
                             const emdq_region *regions, int splitk, int rows,
-                            long long *blocks_out) {
+                            long long *blocks_out, int *tab_rows_out) {
+    int tab_rows = 0;
     int *order = (int *)malloc(sizeof(int) * (size_t)n_pairs);
     if (!order) return EMDQ_ENOMEM;
     for (int i = 0; i < n_pairs; ++i) order[i] = i;
@@ -3388,6 +3566,19 @@ emdq_status fill_field_jobs(FieldJob *jobs, int n_pairs, const emdq_model *model
         const int tiles_y = (r.h + kTile * rows - 1) / (kTile * rows);
         const long long n_tiles = (r.w && r.h) ? (long long)tiles_x * tiles_y : 0;
         J.packed = m->packed;
+        J.xs = m->xs;
+        J.ys = m->ys;
+        J.tabs = FieldTabs{};
+        const long long sxp = (long long)tiles_x * kTile, syp = (long long)tiles_y * kTile * rows;
+        if (m->f32_tab && n_tiles > 0 && sxp + syp <= kF32TabCols) {
+            J.tabs.gx = m->f32_tab;
+            J.tabs.gy = m->f32_tab + (size_t)m->n_max * sxp;
+            J.tabs.sx = (int)sxp;
+            J.tabs.sy = (int)syp;
+            if (tab_rows >= 0) tab_rows = max(tab_rows, m->n_max);
+        } else if (n_tiles > 0) {
+            tab_rows = -1;   // a pair without tables: the whole launch computes in the loop
+        }
         J.st = m->st;
         J.nal2 = -m->alpha * kLog2e;
         J.zx0 = r.zx0;
@@ -3413,15 +3604,31 @@ emdq_status fill_field_jobs(FieldJob *jobs, int n_pairs, const emdq_model *model
         }
     }
     free(order);
+    if (tab_rows < 0) {
+        tab_rows = 0;
+        for (int q = 0; q < n_pairs; ++q) jobs[q].tabs = FieldTabs{};
+    }
     *blocks_out = base;
+    *tab_rows_out = tab_rows;   // 0: no factor tables in this launch
     return EMDQ_OK;
 }
 
 void launch_field_b(int mode, int variant, unsigned blocks, const FieldJob *jobs, int n_jobs,
-                    hipStream_t stream) {
-#define EMDQ_FB(M, K, R)                                                                       \
-    hipLaunchKernelGGL((k_field_b<M, K, R>), dim3(blocks), dim3(kFieldThreads), 0, stream, jobs, \
-                       n_jobs)
+                    int tab_rows, hipStream_t stream) {
+    if (tab_rows > 0)
+        hipLaunchKernelGGL(k_field_tables_b,
+                           dim3((unsigned)((tab_rows + kTabRowsPerThread - 1) / kTabRowsPerThread),
+                                (unsigned)n_jobs),
+                           dim3(kTabThreads), 0, stream, jobs);
+#define EMDQ_FB(M, K, R)                                                                         \
+    do {                                                                                         \
+        if (tab_rows > 0)                                                                        \
+            hipLaunchKernelGGL((k_field_b<M, K, R, true>), dim3(blocks), dim3(kFieldThreads), 0, \
+                               stream, jobs, n_jobs);                                            \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_field_b<M, K, R, false>), dim3(blocks), dim3(kFieldThreads),   \
+                               0, stream, jobs, n_jobs);                                         \
+    } while (0)
     if (mode == kModeField) {
         if (variant == 1) EMDQ_FB(kModeField, 2, 1);
         else if (variant == 2) EMDQ_FB(kModeField, 1, 1);
@@ -3466,14 +3673,15 @@ emdq_status batch_field_launch(emdq_batch b, int n_pairs, const emdq_model *mode
     if (!jobs) return EMDQ_EHIP;
     long long blocks = 0;
     const int v = batch_variant(b, n_pairs, regions);
+    int tab_rows = 0;
     rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[v], kVariantRows[v],
-                         &blocks);
+                         &blocks, &tab_rows);
     if (rc != EMDQ_OK) return rc;
     if (blocks == 0) return EMDQ_OK;
     EMDQ_HIP(hipMemcpyAsync(b->field_jobs, jobs, sizeof(FieldJob) * n_pairs,
                             hipMemcpyHostToDevice, stream));
     EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
-    launch_field_b(mode, v, (unsigned)blocks, b->field_jobs, n_pairs, stream);
+    launch_field_b(mode, v, (unsigned)blocks, b->field_jobs, n_pairs, tab_rows, stream);
     return check_launch();
 }
 
@@ -3805,8 +4013,9 @@ emdq_status emdq_batch_prepare(emdq_batch b, int warp, int n_pairs, const emdq_m
     if (!jobs) return EMDQ_ENOMEM;
     long long blocks = 0;
     const int v = batch_variant(b, n_pairs, regions);
+    int tab_rows = 0;
     rc = fill_field_jobs(jobs, n_pairs, models, regions, kVariantSplitK[v], kVariantRows[v],
-                         &blocks);
+                         &blocks, &tab_rows);
     if (rc == EMDQ_OK &&
         hipMemcpy(b->prepared, jobs, sizeof(FieldJob) * n_pairs, hipMemcpyHostToDevice) !=
             hipSuccess)
@@ -3820,6 +4029,7 @@ emdq_status emdq_batch_prepare(emdq_batch b, int warp, int n_pairs, const emdq_m
     b->prep_pairs = n_pairs;
     b->prep_variant = v;
     b->prep_blocks = blocks;
+    b->prep_tab_rows = tab_rows;
     return EMDQ_OK;
 }
 
@@ -3827,7 +4037,7 @@ emdq_status emdq_batch_launch(emdq_batch b, hipStream_t stream) {
     if (!b || b->prep_mode < 0) return EMDQ_EINVAL;
     if (b->prep_blocks == 0) return EMDQ_OK;
     launch_field_b(b->prep_mode, b->prep_variant, (unsigned)b->prep_blocks, b->prepared,
-                   b->prep_pairs, stream);
+                   b->prep_pairs, b->prep_tab_rows, stream);
     return check_launch();
 }
 
@@ -3848,7 +4058,7 @@ emdq_status emdq_batch_prepare_step(emdq_batch b, int n_pairs, const emdq_model 
     StartJob *st = (StartJob *)(host + sizeof(EmJob) * (size_t)n_pairs);
     FieldJob *fj = (FieldJob *)(host + (sizeof(EmJob) + sizeof(StartJob)) * (size_t)n_pairs);
     BatchEmShape shape;
-    int wgs = 0, v = 0;
+    int wgs = 0, v = 0, tab_rows = 0;
     long long blocks = 0;
     rc = fill_em_jobs(b, em, n_pairs, models, src_xy, dst_xy, n, frame_w, frame_h,
                       start_weights ? (const float *const *)start_p : nullptr, params, &shape);
@@ -3858,7 +4068,7 @@ emdq_status emdq_batch_prepare_step(emdq_batch b, int n_pairs, const emdq_model 
     if (rc == EMDQ_OK) {
         v = batch_variant(b, n_pairs, regions);
         rc = fill_field_jobs(fj, n_pairs, models, regions, kVariantSplitK[v], kVariantRows[v],
-                             &blocks);
+                             &blocks, &tab_rows);
     }
     if (rc == EMDQ_OK &&
         (hipMemcpy(b->step_em, em, sizeof(EmJob) * n_pairs, hipMemcpyHostToDevice) !=
@@ -3876,6 +4086,7 @@ emdq_status emdq_batch_prepare_step(emdq_batch b, int n_pairs, const emdq_model 
     b->step_weights = start_weights;
     b->step_variant = v;
     b->step_blocks = blocks;
+    b->step_tab_rows = tab_rows;
     b->step_shape_blocks = shape.max_blocks;
     b->step_shape_n = shape.max_n;
     b->step_ready = true;
@@ -3896,7 +4107,7 @@ emdq_status emdq_batch_launch_step(emdq_batch b, hipStream_t stream) {
     if (rc != EMDQ_OK) return rc;
     if (b->step_blocks > 0)
         launch_field_b(kModeWarp, b->step_variant, (unsigned)b->step_blocks, b->step_field,
-                       b->step_pairs, stream);
+                       b->step_pairs, b->step_tab_rows, stream);
     return check_launch();
 }
 
