@@ -136,6 +136,11 @@ emdq_status emdq_fit_from(emdq_model m, const float *src_xy, const float *dst_xy
  * (alpha as in emdq_fit for this frame size and params), d = dst - src,
  * ss(t) = t / (1 + |t|);  a network  p = sigmoid(w3 . gelu(W2 gelu(W1 f + b1)
  * + b2) + b3)  with 128-wide GELU layers maps them to a starting posterior.
+ * The two matrix products run on BF16 matrix cores: f, W1, W2 and the first
+ * GELU layer's output are rounded to bfloat16 (nearest, ties to even) and
+ * the products accumulated in FP32; the biases, GELU, the output layer and
+ * the sigmoid are FP32.  The neighbour search uses a grid for pairs of up
+ * to 5120 matches and a scan of every pair above that.
  *   weights  device float[24961]: W1[128][64], b1[128], W2[128][128], b2[128],
  *            w3[128], b3 (row-major), e.g. the trained start_mlp.npy
  *   p_out    device float[n]

@@ -2132,16 +2132,39 @@ static_assert(kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid + kNHid + 1 == 2496
 // Neighbour search of pairs up to kGridMaxN matches: a uniform grid of at
 // most kGridDim x kGridDim cells over the bounding box of the finite source
 // points (about two per cell), counting-sorted into LDS by every workgroup.
-constexpr int kGridMaxN = 4096, kGridDim = 45, kGridMaxCells = kGridDim * kGridDim;
+constexpr int kGridMaxN = 5120, kGridDim = 45, kGridMaxCells = kGridDim * kGridDim;
+static_assert(kGridMaxN % kStartThreads == 0, "grid points split evenly over the threads");
+
+// The network runs on BF16 MFMA (v_mfma_f32_32x32x16_bf16, FP32
+// accumulation) for kMlpRows matches of a wavefront at a time, both layers
+// transposed (outputs x matches):
+//   layer 1  H1^T = W1 F^T:  A = W1 rows (16 features a step), B = the
+//            features of the 32 matches (from LDS);
+//   layer 2  H2^T = W2 H1^T: B = bf16(gelu(H1^T + b1)) taken straight from
+//            layer 1's accumulators.  A lane holds layer-1 outputs o = 32 ob +
+//            8 (r / 4) + 4 (lane / 32) + r % 4 of its match; a K step of 16
+//            contraction slots takes registers r = 8 s .. 8 s + 7 of output
+//            block ob from both halves, i.e. outputs 32 ob + 16 s + 0..15 in
+//            the slot order of w2_col (W2's columns are stored in that order);
+//   output   z = w3 . gelu(H2^T + b2) + b3, summed by each lane over its rows
+//            and across the two halves; p = 1 / (1 + e^-z).
+// Weight rows are padded by 16 bytes against LDS bank conflicts.
+constexpr int kMlpRows = 32;
+constexpr int kW1Stride = kNFeat + 8, kW2Stride = kNHid + 8, kFStride = kNFeat + 8;
+
+// Stored position of W2's column c (layer-1 output c): K step 2 ob + s,
+// slot 8 h + i, for c = 32 ob + 16 s + 4 h + i (i < 4) or + 4 h + i + 4
+// (i >= 4).
+__device__ __forceinline__ int w2_col(int c) {
+    const int t = c & 15;
+    return 16 * (c >> 4) + 8 * ((t >> 2) & 1) + (t & 3) + 4 * (t >> 3);
+}
 
 struct alignas(16) StartLds {
-    // transposed (lane o reads w1t[k][o]); rows padded by one word so that
-    // the transposing stores of a wavefront fall in distinct banks
-    float w1t[kNFeat][kNHid + 1];
-    float w2t[kNHid][kNHid + 1];
+    __bf16 w1[kNHid][kW1Stride];   // W1 rows (features contiguous)
+    __bf16 w2[kNHid][kW2Stride];   // W2 rows, columns stored at w2_col
     float b1[kNHid], b2[kNHid], w3[kNHid];
-    float f[kStartWaves][kNFeat];
-    float h[kStartWaves][kNHid];
+    __bf16 f[kStartWaves][kMlpRows][kFStride];   // features of a wavefront's matches
     float2 gp[kGridMaxN];        // points in cell order
     uint16_t gi[kGridMaxN];      // their match indices
     int gs[kGridMaxCells + 1];   // first point of every cell (counts while built)
@@ -2199,15 +2222,16 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
         for (int k = 0; k < kR1; ++k) r1[k] = W1[tid + k * kStartThreads];
 #pragma unroll
         for (int k = 0; k < kR2; ++k) r2[k] = W2[tid + k * kStartThreads];
+        // rounded to BF16 (nearest, ties to even)
 #pragma unroll
         for (int k = 0; k < kR1; ++k) {
             const int t = tid + k * kStartThreads;
-            L.w1t[t % kNFeat][t / kNFeat] = r1[k];
+            L.w1[t / kNFeat][t % kNFeat] = (__bf16)r1[k];
         }
 #pragma unroll
         for (int k = 0; k < kR2; ++k) {
             const int t = tid + k * kStartThreads;
-            L.w2t[t % kNHid][t / kNHid] = r2[k];
+            L.w2[t / kNHid][w2_col(t % kNHid)] = (__bf16)r2[k];
         }
         for (int t = tid; t < kNHid; t += kStartThreads) {
             L.b1[t] = B1[t];
@@ -2349,7 +2373,19 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
         // gs[c] now holds the end of cell c, i.e. the start of cell c + 1
     }
 
-    for (int i = block * kStartWaves + wave; i < n; i += nblocks * kStartWaves) {
+    // The wavefront's matches i_t = block kStartWaves + wave + t stride, in
+    // groups of kMlpRows: the features of a group's matches first, one match
+    // at a time, then the network on the whole group.
+    const int stride = nblocks * kStartWaves;
+    const int first = block * kStartWaves + wave;
+    for (int g0 = first; g0 < n; g0 += kMlpRows * stride) {
+    for (int r = 0; r < kMlpRows; ++r) {
+        const int i = g0 + r * stride;
+        if (i >= n) {   // rows past the last match: zero features, no output
+            if (!feat_out && lane < kKnn)
+                *(uint2 *)&L.f[wave][r][4 * lane] = make_uint2(0u, 0u);
+            continue;
+        }
         const float2 xi = src[i];
         // ---- per-lane sorted lists of the 16 nearest by (squared distance,
         // index)
@@ -2487,7 +2523,7 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
                 bj[kKnn - 1] = 0x7fffffff;
             }
         }
-        // ---- features (lane r < 16: neighbour r)
+        // ---- features (lane k < 16: neighbour k)
         if (lane < kKnn) {
             float4 fv = make_float4(0.f, 0.f, 0.f, 0.f);
             if (my_nbr >= 0) {
@@ -2497,33 +2533,75 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
                 fv = make_float4(g * (xj.x - xi.x), g * (xj.y - xi.y), ex / (1.f + fabsf(ex)),
                                  ey / (1.f + fabsf(ey)));
             }
-            *(float4 *)&L.f[wave][4 * lane] = fv;
-            if (feat_out) *(float4 *)&feat_out[(size_t)i * kNFeat + 4 * lane] = fv;
+            if (feat_out) {
+                *(float4 *)&feat_out[(size_t)i * kNFeat + 4 * lane] = fv;
+            } else {
+                bhalf4 fb;
+                fb[0] = (__bf16)fv.x;
+                fb[1] = (__bf16)fv.y;
+                fb[2] = (__bf16)fv.z;
+                fb[3] = (__bf16)fv.w;
+                *(bhalf4 *)&L.f[wave][r][4 * lane] = fb;
+            }
         }
-        if (feat_out) continue;
-        wave_sync();   // features are per wavefront: no workgroup barrier
-        // layer 1
-        float a0 = L.b1[lane], a1 = L.b1[lane + 64];
-#pragma unroll 8
-        for (int k = 0; k < kNFeat; ++k) {
-            const float fk = L.f[wave][k];
-            a0 = fmaf(L.w1t[k][lane], fk, a0);
-            a1 = fmaf(L.w1t[k][lane + 64], fk, a1);
+    }
+    if (feat_out) continue;
+    wave_sync();   // features are per wavefront: no workgroup barrier
+    // ---- network on the group (see StartLds).  The weights and biases are
+    // read through lane indices the compiler cannot see as loop-invariant,
+    // so that it does not keep them in registers across the neighbour search.
+    int col = lane & 31, half = lane >> 5;
+    asm volatile("" : "+v"(col), "+v"(half));
+    f32x16 acc1[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc1[ob][q] = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < kNFeat / 16; ++ks) {
+        const bhalf8 fb = *(const bhalf8 *)&L.f[wave][col][16 * ks + 8 * half];
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            const bhalf8 wa = *(const bhalf8 *)&L.w1[32 * ob + col][16 * ks + 8 * half];
+            acc1[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, fb, acc1[ob], 0, 0, 0);
         }
-        L.h[wave][lane] = gelu(a0);
-        L.h[wave][lane + 64] = gelu(a1);
-        wave_sync();
-        // layer 2
-        float c0 = L.b2[lane], c1 = L.b2[lane + 64];
-#pragma unroll 8
-        for (int k = 0; k < kNHid; ++k) {
-            const float hk = L.h[wave][k];
-            c0 = fmaf(L.w2t[k][lane], hk, c0);
-            c1 = fmaf(L.w2t[k][lane + 64], hk, c1);
+    }
+    // layer 2's B operands: K step kk = 2 ob + s takes registers 8 s .. 8 s + 7
+    // of layer 1's output block ob
+    bhalf8 hb[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int ob = kk >> 1, q = 8 * (kk & 1) + t;
+            const int o = 32 * ob + 8 * (q >> 2) + 4 * half + (q & 3);
+            hb[kk][t] = (__bf16)gelu(acc1[ob][q] + L.b1[o]);
         }
-        const float z = wave_sum(L.w3[lane] * gelu(c0) + L.w3[lane + 64] * gelu(c1)) + b3;
-        if (lane == 0) p_out[i] = 1.f / (1.f + expf(-z));
-        wave_sync();   // the next match overwrites this wavefront's rows
+    // layer 2 and the output, one output block at a time
+    float zp = 0.f;
+#pragma unroll 1
+    for (int ob2 = 0; ob2 < 4; ++ob2) {
+        f32x16 acc2;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc2[q] = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            const bhalf8 wa = *(const bhalf8 *)&L.w2[32 * ob2 + col][16 * kk + 8 * half];
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, hb[kk], acc2, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int o = 32 * ob2 + 8 * (q >> 2) + 4 * half + (q & 3);
+            zp += L.w3[o] * gelu(acc2[q] + L.b2[o]);
+        }
+    }
+    // the two halves' sums, added in the same order in both (the shuffle
+    // runs with every lane active)
+    const float zo = __shfl_xor(zp, 32, kWave);
+    const float z = (half == 0 ? zp + zo : zo + zp) + b3;
+    const int im = g0 + col * stride;
+    if (half == 0 && im < n) p_out[im] = 1.f / (1.f + expf(-z));
+    wave_sync();   // the next group overwrites this wavefront's features
     }
 }
 

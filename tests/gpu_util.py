@@ -80,3 +80,25 @@ def fit_prediction_error(src, got, ref):
         b = O.warp_point(ref.scale[i], ref.q[i], x[i, 0], x[i, 1])
         err = max(err, abs(a[0] - b[0]), abs(a[1] - b[1]))
     return err
+
+
+# Learned start (BF16 network): tolerances derived in test_gpu_learned.py.
+START_P_TOL = 2.5e-2     # any match (up to two BF16 rounding steps)
+START_P_TOL_99 = 1e-5    # 99 % of the matches (no rounding step)
+
+
+def check_start(got, want, what):
+    """The learned start against the oracle's BF16 network: every match
+    within START_P_TOL, 99 % within START_P_TOL_99, and the starting mask
+    equal wherever the oracle's p is further than START_P_TOL from 0.5."""
+    got = np.asarray(got, dtype=np.float64)
+    d = np.abs(got - want)
+    q99 = float(np.quantile(d, 0.99))
+    print(f"{what}: start |dp| max {d.max():.2e}, 99% {q99:.2e}", flush=True)
+    assert d.max() <= START_P_TOL and q99 <= START_P_TOL_99
+    clear = np.abs(want - 0.5) > START_P_TOL
+    assert np.array_equal((got > 0.5)[clear], (want > 0.5)[clear])
+
+
+def oracle_start(src, dst, w, h, wo):
+    return O.init_mlp(O.init_features(src, dst, O.alpha(w, h)), wo, bf16=True)

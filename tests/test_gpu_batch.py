@@ -9,7 +9,7 @@ import pytest
 import oracle as O
 from paper_2103_07414_amd import synth
 
-from gpu_util import FIELD_TOL_PX, emdq, to_dev, torch_or_skip
+from gpu_util import FIELD_TOL_PX, check_start, emdq, oracle_start, to_dev, torch_or_skip
 
 pytestmark = pytest.mark.gpu
 
@@ -321,7 +321,10 @@ def _batch64_against_oracle(torch, learned):
         W, H = sizes[i]
         init = None
         if learned:
-            init = O.init_mlp(O.init_features(p.src, p.dst, O.alpha(W, H)), wo)
+            # the start against the oracle's BF16 network, then the oracle's
+            # EM from the same start as the GPU's
+            init = starts[i].cpu().numpy().astype(np.float64)
+            check_start(init, oracle_start(p.src, p.dst, W, H, wo), f"pair {i}")
         ref = O.fit(p.src, p.dst, W, H, init_p=init)
         r = m.results()
         assert r["status"] == ref.status and r["iters"] == ref.iters, (i, r["iters"], ref.iters)

@@ -1,32 +1,37 @@
 """GPU parity of the learned EM start (kNN features + MLP) and of the EM
 started from it, against the FP64 oracle with the same trained weights.
 
-Tolerance of the start: the logit is an FP32 sum of ~200 products of size
-<= ~10 (relative error ~1e-6, so |dz| <~ 1e-4 with erf's own few ulps), and
-|dp| <= |dz| / 4: 1e-4 on p.  The neighbour order is decided in FP64 on both
-sides, so the features are the same up to FP32 rounding.  The EM from the
-start is then held to the plain fit's bar: identical masks and iteration
-counts, field within 1e-3 px."""
+The network's two matrix products take BF16 operands (features, W1, W2 and
+the first hidden layer rounded to bfloat16) on both sides; the GPU
+accumulates in FP32, the oracle sums exactly.  Tolerance of the start: the
+neighbour order is decided in FP64 on both sides, so the features agree to
+FP32 rounding, but an FP32 feature or layer-1 value within ~1e-6 of a BF16
+rounding boundary can round to the neighbouring BF16 value (one step of
+2^-8 relative).  Through the trained weights (|W1| <= 2.0, |W2| <= 2.8,
+|w3| <= 1.3) one such step moves p by at most 1.25e-2: the largest
+first-order change dp/df_k ulp(f_k) or dp/dh_o ulp(h_o) over every match of
+the small, production and learned-start workload pairs.  Any match is held to
+two steps, 2.5e-2.  Without a step the logit is an FP32 sum of ~200 products
+(relative error ~1e-6, |dp| ~ 2e-7 measured), so 99 % of the matches are
+held to 1e-5.  The EM from the start is held to the plain fit's bar against
+the oracle's EM from the same start: identical masks and iteration counts,
+field within 1e-3 px."""
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2103_07414_amd import synth
 
-from gpu_util import FIELD_TOL_PX, emdq, to_dev, torch_or_skip
+from gpu_util import FIELD_TOL_PX, check_start, emdq, oracle_start, to_dev, torch_or_skip
 
 pytestmark = pytest.mark.gpu
-START_P_TOL = 1e-4
-
-
 def _start(E, torch, P):
     w = E.load_start_weights()
     src, dst = to_dev(P.src, torch), to_dev(P.dst, torch)
     out = torch.empty(P.cfg.n_matches, dtype=torch.float32, device="cuda")
     E.emdq_learned_start(src, dst, P.cfg.width, P.cfg.height, w, out)
     wo = np.load(E.START_WEIGHTS, allow_pickle=False).astype(np.float64)
-    a = O.alpha(P.cfg.width, P.cfg.height)
-    want = O.init_mlp(O.init_features(P.src, P.dst, a), wo)
+    want = oracle_start(P.src, P.dst, P.cfg.width, P.cfg.height, wo)
     return src, dst, out, want
 
 
@@ -36,11 +41,27 @@ def test_learned_start_parity(cfg, pair_id):
     E = emdq()
     P = synth.gen_config(cfg, pair_id, with_frame=False)
     _, _, out, want = _start(E, torch, P)
-    got = out.cpu().numpy().astype(np.float64)
-    err = np.abs(got - want).max()
-    print(f"config {cfg}: start max |dp| {err:.2e}, accuracy vs labels "
-          f"{np.mean((got > 0.5) == P.inlier):.4f}", flush=True)
-    assert err <= START_P_TOL
+    got = out.cpu().numpy()
+    print(f"config {cfg}: accuracy vs labels {np.mean((got > 0.5) == P.inlier):.4f}",
+          flush=True)
+    check_start(got, want, f"config {cfg}")
+
+
+def test_learned_start_network_on_gpu_features():
+    """The network alone: the oracle's BF16 network fed the GPU's own
+    features (so only the FP32 accumulation and erf differ)."""
+    torch = torch_or_skip()
+    E = emdq()
+    P = synth.gen_config(5, 2, with_frame=False)
+    src, dst = to_dev(P.src, torch), to_dev(P.dst, torch)
+    W, H = P.cfg.width, P.cfg.height
+    feat = torch.empty((P.cfg.n_matches, 64), dtype=torch.float32, device="cuda")
+    E.emdq_start_features(src, dst, W, H, feat)
+    out = torch.empty(P.cfg.n_matches, dtype=torch.float32, device="cuda")
+    E.emdq_learned_start(src, dst, W, H, E.load_start_weights(), out)
+    wo = np.load(E.START_WEIGHTS, allow_pickle=False).astype(np.float64)
+    want = O.init_mlp(feat.cpu().numpy().astype(np.float64), wo, bf16=True)
+    check_start(out.cpu().numpy(), want, "GPU features")
 
 
 @pytest.mark.parametrize("cfg,pair_id", [(2, 1), (2, 2), (5, 1)])
@@ -53,7 +74,8 @@ def test_em_from_learned_start_parity(cfg, pair_id):
     m = E.Model(P.cfg.n_matches)
     m.fit_from(src, dst, W, H, out)
     got = m.results()
-    ref = O.fit(P.src, P.dst, W, H, init_p=want)
+    # the oracle's EM from the same start
+    ref = O.fit(P.src, P.dst, W, H, init_p=out.cpu().numpy().astype(np.float64))
     plain = O.fit(P.src, P.dst, W, H)
     print(f"config {cfg} pair {pair_id}: iters learned {got['iters']}/{ref.iters} "
           f"plain {plain.iters}", flush=True)

@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 
-from gpu_util import emdq, to_dev, torch_or_skip
+from gpu_util import check_start, emdq, oracle_start, to_dev, torch_or_skip
 
 pytestmark = pytest.mark.gpu
 W, H = 1280, 1024
@@ -44,9 +44,9 @@ def _layout(kind, n, rng):
 
 
 CASES = [("uniform", 2), ("uniform", 5), ("uniform", 17), ("uniform", 2000),
-         ("clusters", 3000), ("duplicates", 1999), ("lattice", 1024), ("lattice", 4096),
+         ("clusters", 3000), ("duplicates", 1999), ("lattice", 1024), ("lattice", 5120),
          ("collinear", 700), ("identical", 40), ("offset", 1500),
-         ("uniform", 4096), ("uniform", 4097)]
+         ("uniform", 5000), ("uniform", 5120), ("uniform", 5121)]
 
 
 @pytest.mark.parametrize("kind,n", CASES)
@@ -65,7 +65,7 @@ def test_start_features_layouts(kind, n):
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("kind,n", [("clusters", 3000), ("lattice", 4096), ("uniform", 4097)])
+@pytest.mark.parametrize("kind,n", [("clusters", 3000), ("lattice", 5120), ("uniform", 5121)])
 def test_learned_start_layouts(kind, n):
     """The whole start (features and network) on the same layouts."""
     torch = torch_or_skip()
@@ -77,7 +77,4 @@ def test_learned_start_layouts(kind, n):
     out = torch.empty(n, dtype=torch.float32, device="cuda")
     E.emdq_learned_start(to_dev(src, torch), to_dev(dst, torch), W, H, E.load_start_weights(), out)
     wo = np.load(E.START_WEIGHTS, allow_pickle=False).astype(np.float64)
-    want = O.init_mlp(O.init_features(src, dst, O.alpha(W, H)), wo)
-    err = np.abs(out.cpu().numpy().astype(np.float64) - want).max()
-    print(f"  max abs err {err:.2e}", flush=True)
-    assert err <= 1e-4
+    check_start(out.cpu().numpy(), oracle_start(src, dst, W, H, wo), f"{kind} n={n}")
