@@ -2132,39 +2132,32 @@ static_assert(kNHid * kNFeat + kNHid + kNHid * kNHid + kNHid + kNHid + 1 == 2496
 // Neighbour search of pairs up to kGridMaxN matches: a uniform grid of at
 // most kGridDim x kGridDim cells over the bounding box of the finite source
 // points (about two per cell), counting-sorted into LDS by every workgroup.
-constexpr int kGridMaxN = 5120, kGridDim = 45, kGridMaxCells = kGridDim * kGridDim;
+constexpr int kGridMaxN = 7168, kGridDim = 50, kGridMaxCells = kGridDim * kGridDim;
 static_assert(kGridMaxN % kStartThreads == 0, "grid points split evenly over the threads");
 
 // The network runs on BF16 MFMA (v_mfma_f32_32x32x16_bf16, FP32
-// accumulation) for kMlpRows matches of a wavefront at a time, both layers
-// transposed (outputs x matches):
+// accumulation) for a block of kMlpRows matches of a workgroup at a time, both
+// layers transposed (outputs x matches):
 //   layer 1  H1^T = W1 F^T:  A = W1 rows (16 features a step), B = the
-//            features of the 32 matches (from LDS);
-//   layer 2  H2^T = W2 H1^T: B = bf16(gelu(H1^T + b1)) taken straight from
-//            layer 1's accumulators.  A lane holds layer-1 outputs o = 32 ob +
-//            8 (r / 4) + 4 (lane / 32) + r % 4 of its match; a K step of 16
-//            contraction slots takes registers r = 8 s .. 8 s + 7 of output
-//            block ob from both halves, i.e. outputs 32 ob + 16 s + 0..15 in
-//            the slot order of w2_col (W2's columns are stored in that order);
-//   output   z = w3 . gelu(H2^T + b2) + b3, summed by each lane over its rows
-//            and across the two halves; p = 1 / (1 + e^-z).
-// Weight rows are padded by 16 bytes against LDS bank conflicts.
+//            block's features (from LDS, rounded to BF16);
+//   layer 2  H2^T = W2 H1^T: B = H1 = bf16(gelu(layer 1 + b1)), written to
+//            LDS by layer 1 (match-major, so it reads like the features);
+//   output   z = w3 . gelu(H2^T + b2) + b3: each lane adds its rows, the two
+//            halves are added, then the four output blocks in block order;
+//            p = 1 / (1 + e^-z).
+// Wavefront w < 4 computes output block w of each layer.  Rows are padded by
+// 16 bytes against LDS bank conflicts.
 constexpr int kMlpRows = 32;
+constexpr int kMlpRounds = kMlpRows / 8;   // rounds of one match per wavefront
 constexpr int kW1Stride = kNFeat + 8, kW2Stride = kNHid + 8, kFStride = kNFeat + 8;
 
-// Stored position of W2's column c (layer-1 output c): K step 2 ob + s,
-// slot 8 h + i, for c = 32 ob + 16 s + 4 h + i (i < 4) or + 4 h + i + 4
-// (i >= 4).
-__device__ __forceinline__ int w2_col(int c) {
-    const int t = c & 15;
-    return 16 * (c >> 4) + 8 * ((t >> 2) & 1) + (t & 3) + 4 * (t >> 3);
-}
-
 struct alignas(16) StartLds {
-    __bf16 w1[kNHid][kW1Stride];   // W1 rows (features contiguous)
-    __bf16 w2[kNHid][kW2Stride];   // W2 rows, columns stored at w2_col
+    __bf16 w1[kNHid][kW1Stride];    // W1 rows (features contiguous)
+    __bf16 w2[kNHid][kW2Stride];    // W2 rows
     float b1[kNHid], b2[kNHid], w3[kNHid];
-    __bf16 f[kStartWaves][kMlpRows][kFStride];   // features of a wavefront's matches
+    __bf16 f[kMlpRows][kFStride];   // features of the block's matches
+    __bf16 h1[kMlpRows][kW2Stride]; // layer-1 output of the block's matches
+    float zpart[4][kMlpRows];       // logit shares of the four output blocks
     float2 gp[kGridMaxN];        // points in cell order
     uint16_t gi[kGridMaxN];      // their match indices
     int gs[kGridMaxCells + 1];   // first point of every cell (counts while built)
@@ -2178,6 +2171,22 @@ struct alignas(16) StartLds {
 
 __device__ __forceinline__ float gelu(float t) {
     return 0.5f * t * (1.f + erff(t * 0.70710678118654752f));
+}
+
+// GELU of the inference network with erf from the rational-exponential
+// approximation of Abramowitz & Stegun (Handbook of Mathematical Functions,
+// formula 7.1.26, after Hastings): erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 +
+// t a5)))) e^(-x^2), t = 1 / (1 + p x), x >= 0, odd in x; absolute error below
+// 1.5e-7.  Branch-free, a third of the instructions of the library erf; the
+// network's inputs to it are then rounded to BF16 or summed into the logit,
+// where this error is far below the BF16 rounding step.
+__device__ __forceinline__ float gelu_fast(float t) {
+    const float x = fabsf(t) * 0.70710678118654752f;
+    const float u = 1.f / (1.f + 0.3275911f * x);
+    const float poly =
+        u * (0.254829592f + u * (-0.284496736f + u * (1.421413741f + u * (-1.453152027f + u * 1.061405429f))));
+    const float e = 1.f - poly * fast_exp2(-kLog2e * x * x);   // erf(|t| / sqrt 2)
+    return 0.5f * t * (1.f + copysignf(e, t));
 }
 
 // (a, ia) < (b, ib) lexicographically
@@ -2231,7 +2240,7 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
 #pragma unroll
         for (int k = 0; k < kR2; ++k) {
             const int t = tid + k * kStartThreads;
-            L.w2[t / kNHid][w2_col(t % kNHid)] = (__bf16)r2[k];
+            L.w2[t / kNHid][t % kNHid] = (__bf16)r2[k];
         }
         for (int t = tid; t < kNHid; t += kStartThreads) {
             L.b1[t] = B1[t];
@@ -2373,17 +2382,19 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
         // gs[c] now holds the end of cell c, i.e. the start of cell c + 1
     }
 
-    // The wavefront's matches i_t = block kStartWaves + wave + t stride, in
-    // groups of kMlpRows: the features of a group's matches first, one match
-    // at a time, then the network on the whole group.
+    // The workgroup's matches in rounds t = 0, 1, ...: in round t wavefront w
+    // takes match (block + t nblocks) kStartWaves + w.  Rounds are grouped by
+    // kMlpRounds: the features of a group's matches (one per wavefront and
+    // round) fill rows 8 (t % kMlpRounds) + w of the workgroup's block, then
+    // the network runs once on the block.
     const int stride = nblocks * kStartWaves;
-    const int first = block * kStartWaves + wave;
-    for (int g0 = first; g0 < n; g0 += kMlpRows * stride) {
-    for (int r = 0; r < kMlpRows; ++r) {
-        const int i = g0 + r * stride;
+    for (int g0 = block * kStartWaves; g0 < n; g0 += kMlpRounds * stride) {   // workgroup-uniform
+    for (int t = 0; t < kMlpRounds; ++t) {
+        const int r = kStartWaves * t + wave;   // row of the block
+        const int i = g0 + t * stride + wave;
         if (i >= n) {   // rows past the last match: zero features, no output
             if (!feat_out && lane < kKnn)
-                *(uint2 *)&L.f[wave][r][4 * lane] = make_uint2(0u, 0u);
+                *(uint2 *)&L.f[r][4 * lane] = make_uint2(0u, 0u);
             continue;
         }
         const float2 xi = src[i];
@@ -2541,67 +2552,67 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
                 fb[1] = (__bf16)fv.y;
                 fb[2] = (__bf16)fv.z;
                 fb[3] = (__bf16)fv.w;
-                *(bhalf4 *)&L.f[wave][r][4 * lane] = fb;
+                *(bhalf4 *)&L.f[r][4 * lane] = fb;
             }
         }
     }
     if (feat_out) continue;
-    wave_sync();   // features are per wavefront: no workgroup barrier
-    // ---- network on the group (see StartLds).  The weights and biases are
-    // read through lane indices the compiler cannot see as loop-invariant,
-    // so that it does not keep them in registers across the neighbour search.
-    int col = lane & 31, half = lane >> 5;
-    asm volatile("" : "+v"(col), "+v"(half));
-    f32x16 acc1[4];
+    __syncthreads();   // the block's features are complete
+    // ---- network on the block (see StartLds): wavefront w < 4 computes
+    // output block w of each layer
+    const int col = lane & 31, half = lane >> 5;
+    if (wave < 4) {
+        const int ob = wave;
+        f32x16 acc;
 #pragma unroll
-    for (int ob = 0; ob < 4; ++ob)
+        for (int q = 0; q < 16; ++q) acc[q] = 0.f;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc1[ob][q] = 0.f;
-#pragma unroll
-    for (int ks = 0; ks < kNFeat / 16; ++ks) {
-        const bhalf8 fb = *(const bhalf8 *)&L.f[wave][col][16 * ks + 8 * half];
-#pragma unroll
-        for (int ob = 0; ob < 4; ++ob) {
+        for (int ks = 0; ks < kNFeat / 16; ++ks) {
             const bhalf8 wa = *(const bhalf8 *)&L.w1[32 * ob + col][16 * ks + 8 * half];
-            acc1[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, fb, acc1[ob], 0, 0, 0);
+            const bhalf8 fb = *(const bhalf8 *)&L.f[col][16 * ks + 8 * half];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, fb, acc, 0, 0, 0);
+        }
+        // H1[match][output] = bf16(gelu(layer 1 + b1))
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int o = 32 * ob + 8 * (q >> 2) + 4 * half + (q & 3);
+            L.h1[col][o] = (__bf16)gelu_fast(acc[q] + L.b1[o]);
         }
     }
-    // layer 2's B operands: K step kk = 2 ob + s takes registers 8 s .. 8 s + 7
-    // of layer 1's output block ob
-    bhalf8 hb[8];
+    __syncthreads();
+    if (wave < 4) {
+        const int ob2 = wave;
+        f32x16 acc;
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk)
+        for (int q = 0; q < 16; ++q) acc[q] = 0.f;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int ob = kk >> 1, q = 8 * (kk & 1) + t;
-            const int o = 32 * ob + 8 * (q >> 2) + 4 * half + (q & 3);
-            hb[kk][t] = (__bf16)gelu(acc1[ob][q] + L.b1[o]);
-        }
-    // layer 2 and the output, one output block at a time
-    float zp = 0.f;
-#pragma unroll 1
-    for (int ob2 = 0; ob2 < 4; ++ob2) {
-        f32x16 acc2;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc2[q] = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
+        for (int kk = 0; kk < kNHid / 16; ++kk) {
             const bhalf8 wa = *(const bhalf8 *)&L.w2[32 * ob2 + col][16 * kk + 8 * half];
-            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, hb[kk], acc2, 0, 0, 0);
+            const bhalf8 hb = *(const bhalf8 *)&L.h1[col][16 * kk + 8 * half];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, hb, acc, 0, 0, 0);
         }
+        // this output block's share of the logit of match col: the lane's 16
+        // rows, then the two halves (same order in both)
+        float zp = 0.f;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int o = 32 * ob2 + 8 * (q >> 2) + 4 * half + (q & 3);
-            zp += L.w3[o] * gelu(acc2[q] + L.b2[o]);
+            zp += L.w3[o] * gelu_fast(acc[q] + L.b2[o]);
         }
+        const float zo = __shfl_xor(zp, 32, kWave);
+        if (half == 0) L.zpart[ob2][col] = zp + zo;
     }
-    // the two halves' sums, added in the same order in both (the shuffle
-    // runs with every lane active)
-    const float zo = __shfl_xor(zp, 32, kWave);
-    const float z = (half == 0 ? zp + zo : zo + zp) + b3;
-    const int im = g0 + col * stride;
-    if (half == 0 && im < n) p_out[im] = 1.f / (1.f + expf(-z));
-    wave_sync();   // the next group overwrites this wavefront's features
+    __syncthreads();
+    if (wave == 0 && lane < kMlpRows) {
+        // the four output blocks' shares added in block order
+        const float z = ((L.zpart[0][lane] + L.zpart[1][lane]) + L.zpart[2][lane]) +
+                        L.zpart[3][lane] + b3;
+        const int im = g0 + (lane / kStartWaves) * stride + lane % kStartWaves;
+        if (im < n) p_out[im] = 1.f / (1.f + expf(-z));
+    }
+    // the next group's features overwrite the block only after the barrier
+    // at its end, so these reads of zpart are done before zpart is written
+    // again
     }
 }
 

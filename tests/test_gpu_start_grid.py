@@ -44,9 +44,9 @@ def _layout(kind, n, rng):
 
 
 CASES = [("uniform", 2), ("uniform", 5), ("uniform", 17), ("uniform", 2000),
-         ("clusters", 3000), ("duplicates", 1999), ("lattice", 1024), ("lattice", 5120),
+         ("clusters", 3000), ("duplicates", 1999), ("lattice", 1024), ("lattice", 7168),
          ("collinear", 700), ("identical", 40), ("offset", 1500),
-         ("uniform", 5000), ("uniform", 5120), ("uniform", 5121)]
+         ("uniform", 5000), ("uniform", 7168), ("uniform", 7169)]
 
 
 @pytest.mark.parametrize("kind,n", CASES)
@@ -65,7 +65,7 @@ def test_start_features_layouts(kind, n):
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("kind,n", [("clusters", 3000), ("lattice", 5120), ("uniform", 5121)])
+@pytest.mark.parametrize("kind,n", [("clusters", 3000), ("lattice", 7168), ("uniform", 7169)])
 def test_learned_start_layouts(kind, n):
     """The whole start (features and network) on the same layouts."""
     torch = torch_or_skip()
