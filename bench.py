@@ -44,16 +44,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpix/s dense EMDQ field+warp (N=2000); EM iters & px error learned vs plain"
 PEAK_TFLOPS = {"f32": 157.3, "f16": 2500.0, "bf16": 2500.0}
-# HBM traffic of the production field + warp kernel per launch, from rocprofv3
-# FETCH_SIZE + WRITE_SIZE (KiB per dispatch) scaled by the copy-kernel
-# calibration (factors 2.0 and 1.0): 15149.4 KiB x 2.0 + 18814.1 KiB x 1.0.
-# Set to None whenever the kernel changes, until the counters are taken again.
-TRAFFIC_BYTES = round((15149.4 * 2.0 + 18814.1 * 1.0) * 1024)
-# Average duration of the same launch in the committed kernel trace of this
-# command (profiles/k_field_warp_f32_1280x1024_n2000.md), beside the live
-# HIP-event duration the roofline fraction is computed from.
-PROFILE = dict(file="profiles/k_field_warp_f32_1280x1024_n2000.md", kernel="k_field<1, 4, 1>",
-               avg_launch_ms=0.21479)
+# HBM traffic of the production warp call (factor-table kernel + blend kernel)
+# per call, from rocprofv3 FETCH_SIZE + WRITE_SIZE (KiB per dispatch) scaled by
+# the copy-kernel calibration (a 256 MiB copy reads FETCH_SIZE 131,085.2 KiB
+# and WRITE_SIZE 262,144.0 KiB): (57.9 + 43,094.6) x 262,144 / 131,085.2 +
+# (12,609.0 + 18,814.1) x 1.0.  Set to None whenever the kernels change,
+# until the counters are taken again.
+TRAFFIC_BYTES = round(((57.9 + 43094.6) * 262144.0 / 131085.2 + (12609.0 + 18814.1)) * 1024)
+# Average duration of the same call in the committed kernel trace of the
+# production command (profiles/k_field_warp_f32_1280x1024_n2000.md): the two
+# kernels' trace averages added, beside the live HIP-event duration the
+# roofline fraction is computed from.
+PROFILE = dict(file="profiles/k_field_warp_f32_1280x1024_n2000.md",
+               kernels=["k_field_tables", "k_field<1, 4, 1, true>"],
+               kernel_avg_us=[8.19, 195.57], avg_launch_ms=0.20376)
 WORKLOADS = ("production", "fhd-f32", "fhd-f16", "fhd-bf16", "batch64", "batch64-learned")
 
 
@@ -387,16 +391,19 @@ def main():
     flops = sum(12.0 * w * h * r["n_in"] for (w, h), r in zip(sizes, res))
     achieved = flops / (warp_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
-    kernel = {"f32": "k_field<warp>", "f16": "k_field_half<warp,f16>",
-              "bf16": "k_field_half<warp,bf16>"}[prec]
+    # the warp call: the factor-table kernel, then the blend kernel
+    kernel = {"f32": "k_field_tables + k_field<warp>",
+              "f16": "k_half_tables<f16> + k_field_half<warp,f16>",
+              "bf16": "k_half_tables<bf16> + k_field_half<warp,bf16>"}[prec]
     if batched:
-        kernel = "k_field_b<warp>"
+        kernel = "k_field_tables_b + k_field_b<warp>"
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4),
                     traffic=TRAFFIC_BYTES if wl == "production" else None, kernel=kernel,
                     algorithmic_flops_per_launch=flops, avg_launch_ms=round(warp_ms, 5),
-                    duration_source="HIP events recorded around every warp launch on the "
-                                    "stream it runs on, mean over the timed steps")
+                    duration_source="HIP events recorded around every warp call (both "
+                                    "kernels) on the stream it runs on, mean over the "
+                                    "timed steps")
     if wl == "production":
         roofline["profile"] = dict(PROFILE, frac_at_profile_duration=round(
             flops / (PROFILE["avg_launch_ms"] * 1e-3) / 1e12 / peak, 4))
