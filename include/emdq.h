@@ -256,7 +256,16 @@ emdq_status emdq_track_nodes(emdq_model m, float beta, int n_nodes, float *pos_x
  *         64 x 128 pixel tile (exact algebra: the blend is linear in the DQ
  *         and the DQ product bilinear), so the rounded values are small
  *         deviations, and the epilogue (normalisation, Eq. (1)) is FP32;
- *   BF16  as F16 with BF16 operands (8-bit significand: about 8x the error).
+ *         FP16's range: a per-axis factor below 2^-14 is subnormal or zero,
+ *         so far from every inlier along an axis (beyond ~1150 px at
+ *         1920 x 1080, ~930 px at 1280 x 1024) FP16 weights lose their
+ *         precision or vanish.  A 64 x 128 tile with a pixel whose weight
+ *         sum is below n_in 2^-13 is therefore blended by the F32 path
+ *         instead (one more launch after the FP16 one; those tiles get the
+ *         F32 mode's bits), so F16 never returns NaN or degraded tiles where
+ *         F32 would not;
+ *   BF16  as F16 with BF16 operands (8-bit significand: about 8x the error;
+ *         FP32's exponent range, so no such fallback).
  * The fit is FP32 in every mode. */
 typedef enum {
     EMDQ_PREC_F32 = 0,
@@ -267,7 +276,8 @@ typedef enum {
 /* Selects the arithmetic of later emdq_field / emdq_warp calls on this
  * model (host-side setting, nothing is enqueued).  The first switch to F16
  * or BF16 allocates the model's factor tables, 2 x 4096 rows of n_max
- * (rounded up to 64) 16-bit values (about 16 KB per unit of n_max), kept
+ * (rounded up to 64) 16-bit values (about 16 KB per unit of n_max; F16 also
+ * 2 KB of tile flags), kept
  * until emdq_model_free; regions larger than 4096 in either direction are
  * processed in slabs.  EINVAL on a null model or an unknown value; ENOMEM. */
 emdq_status emdq_model_set_precision(emdq_model m, emdq_precision precision);

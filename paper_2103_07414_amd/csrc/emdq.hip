@@ -57,6 +57,7 @@ constexpr int kEChunk = EMDQ_ECHUNK;    // matches (+ fits) staged per E-step sw
 constexpr int kCompactThreads = 1024;
 constexpr int kFieldThreads = 256;      // 4 wavefronts per workgroup
 constexpr int kTile = 32;               // 32 x 32 pixels per MFMA output tile
+constexpr int kHTxF = 128, kHTyF = 64;  // workgroup tile of the half-precision blend
 constexpr int kBufferFlags = 0x00020000;   // raw buffer resource word 3 (gfx9 family)
 #ifndef EMDQ_RING
 #define EMDQ_RING 4
@@ -1139,6 +1140,15 @@ struct FieldTabs {
     int sx, sy;
 };
 
+// The tiles an FP16 blend of a region left to the FP32 blend (flags[b] != 0
+// for its tile b, hx tiles per row; see k_field_fallback), and the field
+// output pitch: out[(z_y - zy0) opitch + (z_x - zx0)] (opitch 0: the region
+// width).
+struct FieldFilter {
+    const uint8_t *flags;
+    int hx, opitch;
+};
+
 // RB row blocks of 32 share the B operands: a wavefront's tile is 32 RB rows x
 // 32 columns and each pair of inliers costs RB + 1 exponentials and 6
 // multiplies for 6 RB MFMAs; with factor tables (TAB), RB + 1 table loads
@@ -1148,7 +1158,8 @@ __device__ __forceinline__ void field_body(
     const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
     int zy0, int w, int h, int tiles_x, int n_tiles, float2 *__restrict__ out,
     const uint8_t *__restrict__ frame, int fw, int fh, int fpitch, float4 *__restrict__ canvas,
-    int cpitch, int ox, int oy, int block, FieldTabs tabs = FieldTabs{}) {
+    int cpitch, int ox, int oy, int block, FieldTabs tabs = FieldTabs{},
+    FieldFilter filt = FieldFilter{}) {
     constexpr int kTilesPerWg = 4 / SPLITK;
     constexpr int kRegsOwned = 16 / SPLITK;
     __shared__ FieldLds<SPLITK, RB> lds;
@@ -1163,6 +1174,7 @@ __device__ __forceinline__ void field_body(
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int px0 = zx0 + tx * kTile, py0 = zy0 + ty * kTile * RB;
+    const int opitch = filt.opitch > 0 ? filt.opitch : w;
     const int col = lane & 31, half = lane >> 5;
     const float zcol = (float)(px0 + col);   // z_x of the B operand column
     float zrow[RB];                          // z_y of the A operand rows
@@ -1376,7 +1388,7 @@ __device__ __forceinline__ void field_body(
                                        acc[bl][3][r], acc[bl][4][r], fzx, fzy);
             if constexpr (MODE == kModeField) {
                 if (live[i])
-                    out[(size_t)(zy - zy0) * w + (zx - zx0)] =
+                    out[(size_t)(zy - zy0) * opitch + (zx - zx0)] =
                         bad ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
                             : make_float2(fzx + pd[i].x, fzy + pd[i].y);
             } else if constexpr (!EMDQ_WARP_BATCH) {
@@ -1408,10 +1420,34 @@ __global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(f
     const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
     int zy0, int w, int h, int tiles_x, int n_tiles, float2 *__restrict__ out,
     const uint8_t *__restrict__ frame, int fw, int fh, int fpitch, float4 *__restrict__ canvas,
-    int cpitch, int ox, int oy, FieldTabs tabs) {
+    int cpitch, int ox, int oy, FieldTabs tabs, FieldFilter filt) {
     field_body<MODE, SPLITK, RB, TAB>(packed, st, nal2, zx0, zy0, w, h, tiles_x, n_tiles, out,
                                       frame, fw, fh, fpitch, canvas, cpitch, ox, oy, blockIdx.x,
-                                      tabs);
+                                      tabs, filt);
+}
+
+// The FP32 blend of the tiles an FP16 blend of the same region left
+// (FieldFilter): workgroup b looks at FP16 tile b (64 rows x 128 columns) and,
+// if it is flagged, blends its four 64 x 32 tiles (two 32-row blocks per
+// wavefront, split-K 4) one after the other; unflagged tiles return at once.
+template <int MODE>
+__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_field_fallback(
+    const float4 *__restrict__ packed, const DevState *__restrict__ st, float nal2, int zx0,
+    int zy0, int w, int h, float2 *__restrict__ out, const uint8_t *__restrict__ frame, int fw,
+    int fh, int fpitch, float4 *__restrict__ canvas, int cpitch, int ox, int oy,
+    FieldFilter filt) {
+    if (!filt.flags[blockIdx.x]) return;
+    const int rtx = (w + kTile - 1) / kTile, rty = (h + 2 * kTile - 1) / (2 * kTile);
+    const int hxi = (int)blockIdx.x % filt.hx, hyi = (int)blockIdx.x / filt.hx;
+    const FieldFilter all{nullptr, 0, filt.opitch};
+    for (int k = 0; k < kHTxF / kTile; ++k) {
+        const int tx = (kHTxF / kTile) * hxi + k;
+        if (tx >= rtx) break;   // the same for every thread of the workgroup
+        field_body<MODE, 4, 2, false>(packed, st, nal2, zx0, zy0, w, h, rtx, rtx * rty, out,
+                                      frame, fw, fh, fpitch, canvas, cpitch, ox, oy,
+                                      hyi * rtx + tx, FieldTabs{}, all);
+        __syncthreads();   // the next tile reuses the split-K area of LDS
+    }
 }
 
 // The factor tables of an FP32 blend over a region (FieldTabs): row j of
@@ -1487,8 +1523,9 @@ __global__ __launch_bounds__(kTabThreads) void k_field_tables(
 // into LDS while the MFMAs of the current chunk run (double buffer, one
 // barrier per chunk).
 enum { kDtF16 = 0, kDtBF16 = 1 };
-constexpr int kHTx = 128, kHTy = 64, kHK = 64, kHStride = kHK + 8;   // LDS rows padded
+constexpr int kHTx = kHTxF, kHTy = kHTyF, kHK = 64, kHStride = kHK + 8;   // LDS rows padded
 constexpr int kTabRows = 4096;   // factor-table rows per axis (one slab of the region)
+constexpr int kHalfFlagBytes = (kTabRows / kHTxF) * (kTabRows / kHTyF);   // tiles of a slab
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
@@ -1560,7 +1597,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
     int w, int h, int tiles_x, float2 *__restrict__ out, const uint8_t *__restrict__ frame,
     int fw, int fh, int fpitch, float4 *__restrict__ canvas, int cpitch, int ox, int oy,
     const void *__restrict__ gx_tab, const void *__restrict__ gy_tab, int tab_stride,
-    int opitch) {
+    int opitch, uint8_t *__restrict__ tile_flags) {
     using T = typename HalfT<DT>::T;
     using V8 = typename HalfT<DT>::V8;
     using V4 = typename HalfT<DT>::V4;
@@ -1576,6 +1613,30 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
     const int px0 = zx0 + (int)(blockIdx.x % tiles_x) * kHTx;
     const int py0 = zy0 + (int)(blockIdx.x / tiles_x) * kHTy;
     const float pcx = (float)px0 + 0.5f * (kHTx - 1), pcy = (float)py0 + 0.5f * (kHTy - 1);
+
+    // Table slices of a chunk (with factor tables; see below).  The first
+    // chunk's are loaded before the reference blend, which they do not depend
+    // on, so their latency overlaps it.
+    V8 pgx[kHTx * 8 / kFieldThreads], pgy[kHTy * 8 / kFieldThreads];
+    float4 pr0 = make_float4(0.f, 0.f, 0.f, 0.f), pr1 = pr0;
+    const T *gxw =
+        (const T *)gx_tab + (size_t)(px0 - zx0 + tid / 8) * tab_stride + 8 * (tid % 8);
+    const T *gyw =
+        (const T *)gy_tab + (size_t)(py0 - zy0 + tid / 8) * tab_stride + 8 * (tid % 8);
+    constexpr size_t kRowStep = kFieldThreads / 8;   // rows per piece sweep
+    auto fetch = [&](int jc) {
+#pragma unroll
+        for (int part = 0; part < kHTx * 8 / kFieldThreads; ++part)
+            pgx[part] = *(const V8 *)(gxw + part * kRowStep * tab_stride + jc);
+#pragma unroll
+        for (int part = 0; part < kHTy * 8 / kFieldThreads; ++part)
+            pgy[part] = *(const V8 *)(gyw + part * kRowStep * tab_stride + jc);
+        if (wave == 3 && jc + lane < n_in) {
+            pr0 = packed[2 * (jc + lane)];
+            pr1 = packed[2 * (jc + lane) + 1];
+        }
+    };
+    if (gx_tab && !bad) fetch(0);
 
     // ---- reference at the tile centre: FP32 blend over all inliers
     float sums[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1772,25 +1833,6 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
             // of 16 B.  Workgroup thread e loads pieces e, e + 256, ... in
             // order, so 8 consecutive lanes read one row's aligned 128 B and
             // each load instruction touches 8 cache lines.
-            V8 pgx[kHTx * 8 / kFieldThreads], pgy[kHTy * 8 / kFieldThreads];
-            float4 pr0 = make_float4(0.f, 0.f, 0.f, 0.f), pr1 = pr0;
-            const T *gxw =
-                (const T *)gx_tab + (size_t)(px0 - zx0 + tid / 8) * tab_stride + 8 * (tid % 8);
-            const T *gyw =
-                (const T *)gy_tab + (size_t)(py0 - zy0 + tid / 8) * tab_stride + 8 * (tid % 8);
-            constexpr size_t kRowStep = kFieldThreads / 8;   // rows per piece sweep
-            auto fetch = [&](int jc) {
-#pragma unroll
-                for (int part = 0; part < kHTx * 8 / kFieldThreads; ++part)
-                    pgx[part] = *(const V8 *)(gxw + part * kRowStep * tab_stride + jc);
-#pragma unroll
-                for (int part = 0; part < kHTy * 8 / kFieldThreads; ++part)
-                    pgy[part] = *(const V8 *)(gyw + part * kRowStep * tab_stride + jc);
-                if (wave == 3 && jc + lane < n_in) {
-                    pr0 = packed[2 * (jc + lane)];
-                    pr1 = packed[2 * (jc + lane) + 1];
-                }
-            };
             auto store = [&](int jc, int nb) {
 #pragma unroll
                 for (int part = 0; part < kHTx * 8 / kFieldThreads; ++part)
@@ -1818,8 +1860,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
             // since the previous barrier) and fetches chunk c + 3; chunk
             // c + 1 was stored before the previous barrier, so its first K
             // step is read while chunk c's last MFMAs run.
-            fetch(0);
-            store(0, 0);
+            store(0, 0);   // chunk 0 was fetched before the reference blend
             if (nchunks > 1) {
                 fetch(kHK);
                 store(kHK, 1);
@@ -1878,6 +1919,29 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
                 __syncthreads();
             }
         }
+    }
+
+    // ---- FP16 range: a per-axis factor below FP16's normal range (2^-14)
+    // is subnormal or zero, so inliers far from a pixel along an axis lose
+    // their weight's precision or all of it.  Each such weight is below
+    // 2^-24 in error, so where a pixel's weight sum is at least n_in 2^-13
+    // the weight mass is off by at most 2^-11 of itself; a tile with a pixel
+    // below that is left to the FP32 blend launched after this one
+    // (tile_flags[tile] = 1, nothing written or merged here).
+    if (tile_flags) {
+        const float wmin = (float)n_in * 0x1p-13f;
+        bool low = false;
+#pragma unroll
+        for (int bl = 0; bl < 2; ++bl)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int zx = px0 + 32 * wave + col;
+                const int zy = py0 + 32 * bl + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (zx < zx0 + w && zy < zy0 + h && !(acc[bl][5][r] >= wmin)) low = true;
+            }
+        const bool tile_low = __syncthreads_or(low);
+        if (tid == 0) tile_flags[blockIdx.x] = tile_low ? 1 : 0;
+        if (tile_low) return;
     }
 
     // ---- epilogue: undo the coding, DQ normalisation, Eq. (1); the warp
@@ -2979,6 +3043,7 @@ struct emdq_model_s {
     int precision = EMDQ_PREC_F32;
     void *half_tab = nullptr;   // x and y factor tables of the half-precision blend
     float *f32_tab = nullptr;   // factor tables of the FP32 blend: n_max x kF32TabCols
+    uint8_t *half_flags = nullptr;   // FP16 blend: tiles left to the FP32 blend (one slab)
     int tab_stride = 0;         // values per table row: n_max rounded up to 64
     DevState *st = nullptr;
     DevState *host_st = nullptr;   // pinned
@@ -3066,20 +3131,36 @@ emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h,
                 }
                 // the slab's outputs are addressed through its own origin
                 const unsigned nb = (unsigned)(hx * hy);
+                uint8_t *flags = f16 ? m->half_flags : nullptr;
                 if (mode == kModeField) {
                     auto k = f16 ? k_field_half<kModeField, kDtF16>
                                  : k_field_half<kModeField, kDtBF16>;
                     hipLaunchKernelGGL(k, dim3(nb), dim3(kFieldThreads), 0, stream, m->packed,
                                        m->xs, m->ys, m->st, ka, zx, zy, sw, sh, hx,
                                        out + (size_t)sy * w + sx, nullptr, 0, 0, 0, nullptr, 0, 0,
-                                       0, gxt, gyt, m->tab_stride, w);
+                                       0, gxt, gyt, m->tab_stride, w, flags);
                 } else {
                     auto k = f16 ? k_field_half<kModeWarp, kDtF16>
                                  : k_field_half<kModeWarp, kDtBF16>;
                     hipLaunchKernelGGL(k, dim3(nb), dim3(kFieldThreads), 0, stream, m->packed,
                                        m->xs, m->ys, m->st, ka, zx, zy, sw, sh, hx, nullptr,
                                        frame, fw, fh, fpitch, canvas, cpitch, ox, oy, gxt, gyt,
-                                       m->tab_stride, w);
+                                       m->tab_stride, w, flags);
+                }
+                if (flags) {
+                    // the tiles the FP16 blend left, in FP32 (one workgroup per FP16 tile)
+                    const FieldFilter filt{flags, hx, w};
+                    const float nal2 = -m->alpha * kLog2e;
+                    if (mode == kModeField)
+                        hipLaunchKernelGGL(k_field_fallback<kModeField>, dim3(nb),
+                                           dim3(kFieldThreads), 0, stream, m->packed, m->st, nal2,
+                                           zx, zy, sw, sh, out + (size_t)sy * w + sx, nullptr, 0,
+                                           0, 0, nullptr, 0, 0, 0, filt);
+                    else
+                        hipLaunchKernelGGL(k_field_fallback<kModeWarp>, dim3(nb),
+                                           dim3(kFieldThreads), 0, stream, m->packed, m->st, nal2,
+                                           zx, zy, sw, sh, nullptr, frame, fw, fh, fpitch, canvas,
+                                           cpitch, ox, oy, filt);
                 }
             }
         return check_launch();
@@ -3103,7 +3184,8 @@ emdq_status launch_field(emdq_model m, int mode, int zx0, int zy0, int w, int h,
 #define EMDQ_F(M, R, T, O, F, C)                                                                \
     hipLaunchKernelGGL((k_field<M, kSplitK, R, T>), dim3((unsigned)blocks),                  \
                        dim3(kFieldThreads), 0, stream, m->packed, m->st, nal2, zx0, zy0, w, h, \
-                       tiles_x, (int)n_tiles, O, F, fw, fh, fpitch, C, cpitch, ox, oy, tabs)
+                       tiles_x, (int)n_tiles, O, F, fw, fh, fpitch, C, cpitch, ox, oy, tabs, \
+                       FieldFilter{})
 #define EMDQ_FT(M, R, O, F, C)                 \
     do {                                       \
         if (tabs.gx) EMDQ_F(M, R, true, O, F, C); \
@@ -3232,6 +3314,7 @@ void emdq_model_free(emdq_model m) {
     (void)hipFree(m->ys);
     (void)hipFree(m->half_tab);
     (void)hipFree(m->f32_tab);
+    (void)hipFree(m->half_flags);
     (void)hipFree(m->st);
     if (m->host_st) (void)hipHostFree(m->host_st);
     if (m->em_st) (void)hipHostFree(m->em_st);
@@ -3502,6 +3585,17 @@ emdq_status emdq_model_set_precision(emdq_model m, emdq_precision precision) {
     if (precision != EMDQ_PREC_F32 && precision != EMDQ_PREC_F16 &&
         precision != EMDQ_PREC_BF16)
         return EMDQ_EINVAL;
+    if (precision == EMDQ_PREC_F16 && !m->half_flags) {
+        int prev = 0;
+        if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(m->device) != hipSuccess)
+            return EMDQ_EHIP;
+        const hipError_t e = hipMalloc((void **)&m->half_flags, kHalfFlagBytes);
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess) {
+            m->half_flags = nullptr;
+            return EMDQ_ENOMEM;
+        }
+    }
     if (EMDQ_HALF_TABLES && precision != EMDQ_PREC_F32 && !m->half_tab) {
         const int stride = (m->n_max + 63) / 64 * 64;
         const size_t bytes = (size_t)2 * kTabRows * (size_t)stride * 2;

@@ -208,3 +208,72 @@ def test_field_small_inlier_counts(prec):
         assert m.results()["n_in"] == n_keep
         assert rc == 0 and err <= tol, (prec, n_keep, err)
     m.close()
+
+
+def _corner_nodes(n, seed):
+    """Node fits only in the top-left 250 x 250 px of a 1920 x 1080 region:
+    one similarity (rotation 0.03 rad, scale 1.01, shift (4, -3) px) with
+    small per-node departures (1e-4 rad, 0.2 px, 1e-4), so that the FP16
+    deviation coding stays accurate across the region (its coded
+    translations grow with the rotation departure times the coordinate) and
+    the test isolates the FP16 range."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform([0, 0], [250, 250], (n, 2)).astype(np.float32)
+    th = 0.03 + rng.uniform(-1e-4, 1e-4, n)
+    tx, ty = 4.0 + rng.uniform(-0.2, 0.2, n), -3.0 + rng.uniform(-0.2, 0.2, n)
+    c, s = np.cos(th / 2), np.sin(th / 2)
+    q = np.stack([c, s, (c * tx + s * ty) / 2, (c * ty - s * tx) / 2], 1).astype(np.float32)
+    scale = (1.01 + rng.uniform(-1e-4, 1e-4, n)).astype(np.float32)
+    return x, scale, q
+
+
+def test_f16_far_from_every_inlier_uses_the_f32_blend():
+    """FP16 range: pixels more than ~1150 px from every node along an axis
+    get no FP16 weight (and pixels a little closer only subnormal weights).
+    Such tiles are blended in FP32 instead: no NaN, the whole field within
+    the FP16 bar of the oracle, and the far tiles bit-identical to the FP32
+    mode (the same kernel and bits there)."""
+    torch = torch_or_skip()
+    E = emdq()
+    W, H, n = 1920, 1080, 300
+    x, scale, q = _corner_nodes(n, 5)
+    alpha = float(np.float32(O.alpha(W, H)))
+    outs = {}
+    for prec in ("f16", "f32"):
+        m = E.Model(n)
+        m.set_precision(prec)
+        m.set_nodes(x, scale, q, None, alpha)
+        outs[prec] = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+        m.field(0, 0, W, H, outs[prec])
+    f16, f32 = outs["f16"].cpu().numpy(), outs["f32"].cpu().numpy()
+    assert np.isfinite(f16).all()
+    rc, want = O.field(x, scale.astype(np.float64), q.astype(np.float64), np.ones(n, np.uint8),
+                       alpha, 0, 0, W, H)
+    err = float(np.abs(f16 - want).max())
+    far = np.array_equal(f16[:, 1536:], f32[:, 1536:])
+    print(f"f16 corner nodes: max err {err:.2e} px, far tiles equal to f32: {far}", flush=True)
+    assert rc == 0 and err <= HALF_TOL_PX["f16"]
+    assert far
+
+
+def test_f16_warp_far_from_every_inlier_uses_the_f32_blend():
+    """The same in warp mode: the far tiles merge exactly what the FP32 mode
+    merges, and the FP16 canvas stays within one level of the FP32 one."""
+    torch = torch_or_skip()
+    E = emdq()
+    W, H, n = 1920, 1080, 300
+    x, scale, q = _corner_nodes(n, 6)
+    alpha = float(np.float32(O.alpha(W, H)))
+    rng = np.random.default_rng(9)
+    frame = to_dev(rng.integers(0, 256, (H, W, 3)).astype(np.uint8), torch)
+    canv = {}
+    for prec in ("f16", "f32"):
+        m = E.Model(n)
+        m.set_precision(prec)
+        m.set_nodes(x, scale, q, None, alpha)
+        canv[prec] = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+        m.warp(frame, canv[prec], 0, 0, 0, 0, W, H)
+    a, b = canv["f16"].cpu().numpy(), canv["f32"].cpu().numpy()
+    assert np.array_equal(a[:, 1536:], b[:, 1536:])
+    assert np.abs(a[..., :3] - b[..., :3]).max() <= COLOUR_TOL + 1e-3
+    assert (a[..., 3] > 0).sum() > 0.9 * W * H
