@@ -509,6 +509,26 @@ class Batch:
     def _handles(models):
         return (C.c_void_p * len(models))(*[m.handle for m in models])
 
+    @staticmethod
+    def _pairs(models, srcs, dsts, sizes):
+        """The per-pair match arrays and frame sizes of fit / prepare_step as
+        C arrays: src, dst pointers, n, frame_w, frame_h."""
+        import torch
+        k = len(models)
+        if not (len(srcs) == len(dsts) == len(sizes) == k):
+            raise ValueError("models, srcs, dsts and sizes must have the same length")
+        ps, pd, ns = [], [], []
+        for m, a, b in zip(models, srcs, dsts):
+            if a.shape != b.shape or a.dim() != 2 or a.shape[1] != 2:
+                raise ValueError("src and dst must both be [N, 2]")
+            ps.append(_dev(a, torch.float32, "src"))
+            pd.append(_dev(b, torch.float32, "dst"))
+            ns.append(int(a.shape[0]))
+            m.n = int(a.shape[0])
+        arr = lambda v, t: (t * k)(*v)
+        return (arr(ps, C.c_void_p), arr(pd, C.c_void_p), arr(ns, C.c_int),
+                arr([w for w, _ in sizes], C.c_int), arr([h for _, h in sizes], C.c_int))
+
     def learned_start(self, srcs, dsts, sizes, weights, outs, params=None, stream=None):
         """Learned starting posteriors of every pair in one launch: outs are
         CUDA float32 [N_i]; weights as load_start_weights()."""
@@ -540,26 +560,14 @@ class Batch:
         CUDA float32 [N_i] starting posteriors per pair."""
         import torch
         k = len(models)
-        if not (len(srcs) == len(dsts) == len(sizes) == k):
-            raise ValueError("models, srcs, dsts and sizes must have the same length")
+        cs = self._pairs(models, srcs, dsts, sizes)
         pi = None
         if init_ps is not None:
             if len(init_ps) != k:
                 raise ValueError("init_ps must have one entry per pair")
             pi = (C.c_void_p * k)(*[_dev(t, torch.float32, "init_p") for t in init_ps])
-        ps, pd, ns = [], [], []
-        for m, a, b in zip(models, srcs, dsts):
-            if a.shape != b.shape or a.dim() != 2 or a.shape[1] != 2:
-                raise ValueError("src and dst must both be [N, 2]")
-            ps.append(_dev(a, torch.float32, "src"))
-            pd.append(_dev(b, torch.float32, "dst"))
-            ns.append(int(a.shape[0]))
-            m.n = int(a.shape[0])
-        arr = lambda v, t: (t * k)(*v)
         return _check(lib().emdq_batch_fit(
-            self.handle, k, self._handles(models), arr(ps, C.c_void_p), arr(pd, C.c_void_p),
-            arr(ns, C.c_int), arr([w for w, _ in sizes], C.c_int),
-            arr([h for _, h in sizes], C.c_int), pi,
+            self.handle, k, self._handles(models), *cs, pi,
             C.byref(params) if params is not None else None, _stream(stream)),
             "emdq_batch_fit")
 
@@ -640,18 +648,9 @@ class Batch:
         from it (else from p = 1), and the batched warp."""
         import torch
         k = len(models)
-        if not (len(srcs) == len(dsts) == len(sizes) == k):
-            raise ValueError("models, srcs, dsts and sizes must have the same length")
         if (weights is None) != (starts is None):
             raise ValueError("weights and starts go together")
-        ps, pd, ns = [], [], []
-        for m, a, b in zip(models, srcs, dsts):
-            if a.shape != b.shape or a.dim() != 2 or a.shape[1] != 2:
-                raise ValueError("src and dst must both be [N, 2]")
-            ps.append(_dev(a, torch.float32, "src"))
-            pd.append(_dev(b, torch.float32, "dst"))
-            ns.append(int(a.shape[0]))
-            m.n = int(a.shape[0])
+        cs = self._pairs(models, srcs, dsts, sizes)
         arr = lambda v, t: (t * k)(*v)
         pw, pst = None, None
         if weights is not None:
@@ -665,10 +664,9 @@ class Batch:
         regs = self._warp_regions(models, frames, canvases, offsets, rects)
         self._keep_step = (models, srcs, dsts, frames, canvases, weights, starts)
         return _check(lib().emdq_batch_prepare_step(
-            self.handle, k, self._handles(models), arr(ps, C.c_void_p), arr(pd, C.c_void_p),
-            arr(ns, C.c_int), arr([w for w, _ in sizes], C.c_int),
-            arr([h for _, h in sizes], C.c_int), C.byref(params) if params is not None else None,
-            pw, pst, regs), "emdq_batch_prepare_step")
+            self.handle, k, self._handles(models), *cs,
+            C.byref(params) if params is not None else None, pw, pst, regs),
+            "emdq_batch_prepare_step")
 
     def launch_step(self, stream=None):
         """The prepared step: no copy, no host synchronisation, capturable in

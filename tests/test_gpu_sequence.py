@@ -80,3 +80,43 @@ def test_sequence_mosaic_and_nodes_match_oracle():
           f"border-excluded {near.sum()}", flush=True)
     assert d[:, 3].max() == 0.0 and d[:, :3].max() <= 1.0
     assert (got[oy:oy + H, ox:ox + W, 3] > 0).mean() > 0.5      # the frames were merged
+
+
+def test_merge_weight_cap_reached():
+    """35 merges into one canvas, alternating two frames through one fitted
+    field: the merge count saturates at 30 after 30 merges (Eqs. (23)-(24)
+    with the cap), after which the colour is a moving average.  Every canvas
+    pixel equals the oracle's after the same 35 merges (colour within one
+    level; counts exactly), away from the frame border."""
+    torch = torch_or_skip()
+    E = emdq()
+    P = synth.gen_config(1, 2)
+    Q = synth.gen_config(1, 4)   # a second texture of the same size
+    W, H = P.cfg.width, P.cfg.height
+    cw, ch, ox, oy = synth.canvas_layout(P.cfg)
+    ref = oracle_fit(P)
+    m = E.Model(P.cfg.n_matches)
+    s32 = ref.scale.astype(np.float32)
+    q32 = ref.q.astype(np.float32)
+    alpha = float(np.float32(ref.alpha))
+    m.set_nodes(P.src, s32, q32, ref.mask, alpha)
+    frames = [P.frame, Q.frame]
+    g_frames = [to_dev(f, torch) for f in frames]
+    g_canvas = torch.zeros((ch, cw, 4), dtype=torch.float32, device="cuda")
+    o_canvas = np.zeros((ch, cw, 4))
+    for k in range(35):
+        m.warp(g_frames[k % 2], g_canvas, ox, oy, 0, 0, W, H)
+        rc, o_canvas, _ = O.warp(P.src, s32.astype(np.float64), q32.astype(np.float64),
+                                 ref.mask, alpha, frames[k % 2], o_canvas, ox, oy, 0, 0, W, H)
+        assert rc == 0
+    _, u = O.field(P.src, s32.astype(np.float64), q32.astype(np.float64), ref.mask, alpha,
+                   0, 0, W, H)
+    keep = np.ones((ch, cw), bool)
+    keep[oy:oy + H, ox:ox + W] = ~border_mask(u, W, H)
+    got = g_canvas.cpu().numpy()
+    d = np.abs(got - o_canvas)[keep]
+    a = got[oy:oy + H, ox:ox + W, 3]
+    print(f"35 merges: max colour err {d[:, :3].max():.3e}, counts at the cap "
+          f"{(a == 30).mean():.3f}", flush=True)
+    assert d[:, 3].max() == 0.0 and d[:, :3].max() <= 1.0
+    assert (a == 30).mean() > 0.9 and a.max() == 30
