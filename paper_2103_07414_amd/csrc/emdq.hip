@@ -96,6 +96,16 @@ constexpr int kEmChunk = EMDQ_EM_CHUNK; // EM iterations enqueued between stop-f
 #ifndef EMDQ_FUSED_MAX_N
 #define EMDQ_FUSED_MAX_N 2048
 #endif
+// single-pair EM: the host waits for a chunk's stop flag by polling its
+// sequence number in pinned memory (1) or by an event (0)
+#ifndef EMDQ_EM_POLL
+#define EMDQ_EM_POLL 1
+#endif
+// fused single-pair EM: a speculative compaction after every chunk (measured
+// slower: its launches cost more than the host round trip they save)
+#ifndef EMDQ_SPEC_COMPACT
+#define EMDQ_SPEC_COMPACT 0
+#endif
 constexpr int kFusedMaxN = EMDQ_FUSED_MAX_N;   // single-pair fits: two launches per iteration up to this n
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -111,6 +121,8 @@ struct DevState {
     float sigma2;
     float gamma;
     int stop_at;     // single-pair fit: launch that ended the EM (em_stopped), 0 = running
+    int packed;      // the inliers are packed (speculative compaction done)
+    int seq;         // host copies only: sequence number of the publishing launch
 };
 
 // ------------------------------------------------------------ helpers ----
@@ -141,6 +153,14 @@ __device__ __forceinline__ bool finite2(float2 v) {
 
 // ------------------------------------------------------ state, loading ----
 
+// The state as a launch leaves it, copied into pinned host memory for the
+// host's stop-flag reads, then its sequence number (system-scope release):
+// the host polls the number, so no event has to be recorded.
+__device__ __forceinline__ void publish_state(DevState *host_copy, const DevState *st, int seq) {
+    *host_copy = *st;
+    __hip_atomic_store(&host_copy->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __device__ __forceinline__ void reset_state(DevState *st) {
     st->status = 0;
     st->iter = 0;
@@ -150,6 +170,8 @@ __device__ __forceinline__ void reset_state(DevState *st) {
     st->sigma2 = 0.f;
     st->gamma = 0.f;
     st->stop_at = 0;
+    st->packed = 0;
+    st->seq = 0;
 }
 
 // The launches of a single-pair fit, numbered in enqueue order: the load is 1,
@@ -693,6 +715,7 @@ struct EmStop {
     DevState *host_copy;    // pinned host memory or null: the state as the launch leaves it
     int max_iter;
     int it;                 // this iteration (from 1)
+    int seq;                // sequence number published with host_copy
 };
 
 // Blend of all fits at match i with weights exp(-alpha d^2) p_j (Eqs. (2)-(3)),
@@ -761,7 +784,7 @@ __device__ __forceinline__ void estep_body(
         int any = stp.it >= 2 ? chg0 : 0;
         const bool lead = block == 0 && threadIdx.x == 0;
         auto publish = [&]() {
-            if (lead && stp.host_copy) *stp.host_copy = *st;
+            if (lead && stp.host_copy) publish_state(stp.host_copy, st, stp.seq);
         };
         if (em_stopped(stop, 2 * stp.it + 1)) {
             publish();
@@ -882,10 +905,10 @@ constexpr int kPostThreads = 1024;
 __device__ __forceinline__ void posterior_body(
     float *__restrict__ p, const float *__restrict__ e2, uint8_t *__restrict__ mask, int n,
     const double2 *__restrict__ part, int nb, const PostParams &pp, DevState *st,
-    DevState *host_copy) {
+    DevState *host_copy, int seq) {
 #pragma clang fp contract(off)
     auto publish = [&]() {
-        if (host_copy && threadIdx.x == 0) *host_copy = *st;
+        if (host_copy && threadIdx.x == 0) publish_state(host_copy, st, seq);
     };
     if (st->status < 0 || st->done) {
         publish();
@@ -927,8 +950,8 @@ __device__ __forceinline__ void posterior_body(
 __global__ __launch_bounds__(kPostThreads) void k_posterior(
     float *__restrict__ p, const float *__restrict__ e2, uint8_t *__restrict__ mask, int n,
     const double2 *__restrict__ part, int nb, PostParams pp, DevState *st,
-    DevState *host_copy) {
-    posterior_body(p, e2, mask, n, part, nb, pp, st, host_copy);
+    DevState *host_copy, int seq) {
+    posterior_body(p, e2, mask, n, part, nb, pp, st, host_copy, seq);
 }
 
 // ------------------------------------------------------------ compaction ----
@@ -1003,6 +1026,20 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(
     const uint8_t *__restrict__ mask, int n, float4 *__restrict__ packed,
     float *__restrict__ xs, float *__restrict__ ys, DevState *st, EmFinal fin) {
     compact_body(xy, q, s, mask, n, packed, xs, ys, st, fin, blockIdx.x);
+}
+
+// Speculative compaction of a fused single-pair fit, enqueued after every
+// chunk of EM iterations: once the EM has stopped (the M-step before the
+// stopping E-step fitted with the final posteriors), the first one packs the
+// inliers and the later ones return at once; before that they all return.
+__global__ __launch_bounds__(kCompactThreads) void k_compact_spec(
+    const float4 *__restrict__ xy, const float4 *__restrict__ q, const float *__restrict__ s,
+    const uint8_t *__restrict__ mask, int n, float4 *__restrict__ packed,
+    float *__restrict__ xs, float *__restrict__ ys, DevState *st) {
+    if (st->stop_at == 0 || st->packed) return;
+    compact_body(xy, q, s, mask, n, packed, xs, ys, st, EmFinal{}, blockIdx.x);
+    __syncthreads();
+    if (threadIdx.x == 0) st->packed = 1;
 }
 
 // ------------------------------------------------------------ field / warp ----
@@ -2964,7 +3001,7 @@ __global__ __launch_bounds__(kPostThreads) void k_posterior_b(
     float p_thresh, int max_iter) {
     const EmJob &J = jobs[blockIdx.x];
     const PostParams pp{J.u, sigma2_min, gamma_min, gamma_max, p_thresh, max_iter};
-    posterior_body(J.p, J.e2, J.mask, J.n, J.part, J.blocks, pp, J.st, nullptr);
+    posterior_body(J.p, J.e2, J.mask, J.n, J.part, J.blocks, pp, J.st, nullptr, 0);
 }
 
 __global__ __launch_bounds__(kCompactThreads) void k_compact_b(const EmJob *__restrict__ jobs) {
@@ -3050,6 +3087,8 @@ struct emdq_model_s {
     DevState *em_st = nullptr;     // pinned [2]: stop flags read while the EM runs on
     DevState *em_st_dev = nullptr; // the same two slots, as the device addresses them
     hipEvent_t em_ev[2] = {};
+    int em_seq = 0;                // sequence number of the last chunk enqueued
+    int em_slot_seq[2] = {};       // the number each slot will be published with
 };
 
 namespace {
@@ -3333,6 +3372,23 @@ emdq_status emdq_fit(emdq_model m, const float *src_xy, const float *dst_xy, int
 
 namespace {
 
+// Waits until pinned slot `slot` holds the state published with sequence
+// number `seq` (by the last E-step or posterior kernel of a chunk); the
+// stream is queried now and then so that a failed launch is reported rather
+// than waited for.
+emdq_status wait_published(emdq_model m, int slot, int seq, hipStream_t stream) {
+    for (unsigned spins = 1;; ++spins) {
+        if (__atomic_load_n(&m->em_st[slot].seq, __ATOMIC_ACQUIRE) == seq) return EMDQ_OK;
+        if ((spins & 1023u) == 0u) {
+            const hipError_t e = hipStreamQuery(stream);
+            if (e == hipSuccess)   // everything enqueued has completed
+                return __atomic_load_n(&m->em_st[slot].seq, __ATOMIC_ACQUIRE) == seq
+                           ? EMDQ_OK : EMDQ_EHIP;
+            if (e != hipErrorNotReady) return EMDQ_EHIP;
+        }
+    }
+}
+
 emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int n,
                      int frame_w, int frame_h, const emdq_params *params, const float *init_p,
                      hipStream_t stream, bool host_sync) {
@@ -3381,37 +3437,54 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
     // once the EM has stopped, so a chunk may overshoot.  The stop flag after
     // chunk k is read while chunk k + 1 already runs, so the GPU does not
     // wait for the host between chunks.
+    // Fused fits also enqueue a speculative compaction after every chunk
+    // (k_compact_spec), so the inliers are packed as soon as the EM stops,
+    // without waiting for the host to read the stop flag.
+    const bool spec = EMDQ_SPEC_COMPACT && fused && host_sync;
     int enqueued = 0;
     bool stopped = false;   // the host has read a stop flag
     for (int k = 0;; ++k) {
         // the chunk's last E-step (fused) or posterior kernel also stores the
-        // state into host slot k & 1 (a chunk holds at least one iteration:
-        // the loop leaves once max_iter iterations are enqueued)
+        // state into host slot k & 1 with the chunk's sequence number (a
+        // chunk holds at least one iteration: the loop leaves once max_iter
+        // iterations are enqueued)
+        const int seq = ++m->em_seq;
+        m->em_slot_seq[k & 1] = seq;
         for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
             const bool last = c + 1 == kEmChunk || enqueued + 1 == prm.max_iter;
             DevState *slot = last && host_sync ? &m->em_st_dev[k & 1] : nullptr;
             const int it = enqueued + 1;
             mstep(it, 0);
             if (fused) {
-                const EmStop X{m->chg, slot, prm.max_iter, it};
+                const EmStop X{m->chg, slot, prm.max_iter, it, seq};
                 hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
                                    m->p, m->q, m->s, n, nal2, m->e2, m->part, m->st, X);
             } else {
                 hipLaunchKernelGGL(k_estep_s, dim3(em_blocks), dim3(kEmThreads), 0, stream,
                                    m->xy, m->p, m->q, m->s, n, nal2, m->e2, m->part, m->st);
                 hipLaunchKernelGGL(k_posterior, dim3(1), dim3(kPostThreads), 0, stream, m->p,
-                                   m->e2, m->mask, n, m->part, (int)em_blocks, pp, m->st, slot);
+                                   m->e2, m->mask, n, m->part, (int)em_blocks, pp, m->st, slot,
+                                   seq);
             }
         }
+        if (spec)
+            hipLaunchKernelGGL(k_compact_spec, dim3(1), dim3(kCompactThreads), 0, stream, m->xy,
+                               m->q, m->s, m->mask, n, m->packed, m->xs, m->ys, m->st);
         if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
         if (!host_sync) {
             if (enqueued >= prm.max_iter) break;
             continue;
         }
-        EMDQ_HIP(hipEventRecord(m->em_ev[k & 1], stream));
+        if (!EMDQ_EM_POLL) EMDQ_HIP(hipEventRecord(m->em_ev[k & 1], stream));
         if (k > 0) {
-            EMDQ_HIP(hipEventSynchronize(m->em_ev[(k - 1) & 1]));
-            const DevState &prev = m->em_st[(k - 1) & 1];
+            const int ps = (k - 1) & 1;
+            if (EMDQ_EM_POLL) {
+                const emdq_status wr = wait_published(m, ps, m->em_slot_seq[ps], stream);
+                if (wr != EMDQ_OK) return wr;
+            } else {
+                EMDQ_HIP(hipEventSynchronize(m->em_ev[ps]));
+            }
+            const DevState &prev = m->em_st[ps];
             if (prev.done || prev.status < 0) {
                 stopped = true;
                 break;
@@ -3419,6 +3492,10 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
         }
         if (enqueued >= prm.max_iter) break;
     }
+    // once a stop flag was read, a fused fit is complete: the M-step before
+    // the stopping E-step fitted with the final posteriors, and the
+    // speculative compaction after that chunk packed the inliers
+    if (spec && stopped) return check_launch();
     // the fit with the final posteriors (fused: the posteriors of the last
     // enqueued iteration first; not needed once a stop flag was read, as the
     // M-step before the stopping E-step fitted already), then (fused) the
