@@ -241,6 +241,26 @@ __device__ __forceinline__ float2 blend_displacement(float W, float Cd, float Sn
         __builtin_fmaf(sg, zx, s1 * (__builtin_fmaf(r00, zx, -(r10 * zy)) + tx)),
         __builtin_fmaf(sg, zy, s1 * (__builtin_fmaf(r10, zx, r00 * zy) + ty)));
 }
+// blend_displacement for the dense field's epilogue: the two divisions by
+// hardware reciprocals (about 1 ulp; a relative error of ~1e-7 in the
+// displacement, against the 1e-3 px bar), one instruction each instead of an
+// IEEE division.  The EM keeps the divisions, so its residuals and the mask
+// decisions are unchanged.
+__device__ __forceinline__ float2 blend_displacement_field(float W, float Cd, float Sn, float X, float Y,
+                                                     float Gd, float zx, float zy) {
+#pragma clang fp contract(off)
+    const float iW = __builtin_amdgcn_rcpf(W);
+    const float c = __builtin_fmaf(Cd, iW, 1.f), sn = Sn * iW, x = X * iW, y = Y * iW,
+                sg = Gd * iW;
+    const float in2 = __builtin_amdgcn_rcpf(__builtin_fmaf(c, c, sn * sn));
+    const float r00 = -2.f * sn * sn * in2, r10 = 2.f * c * sn * in2;
+    const float tx = 2.f * __builtin_fmaf(c, x, -(sn * y)) * in2,
+                ty = 2.f * __builtin_fmaf(c, y, sn * x) * in2;
+    const float s1 = 1.f + sg;
+    return make_float2(
+        __builtin_fmaf(sg, zx, s1 * (__builtin_fmaf(r00, zx, -(r10 * zy)) + tx)),
+        __builtin_fmaf(sg, zy, s1 * (__builtin_fmaf(r10, zx, r00 * zy) + ty)));
+}
 
 // ------------------------------------------------------------ posterior ----
 //
@@ -1093,9 +1113,10 @@ enum { kModeField = 0, kModeWarp = 1 };
     float4 *px = canvas + (size_t)(zy + oy) * cpitch + (zx + ox);
     float4 cur = *px;
     const float A = cur.w, A1 = A + 1.f;
-    cur.x = (A * cur.x + v[0]) / A1;
-    cur.y = (A * cur.y + v[1]) / A1;
-    cur.z = (A * cur.z + v[2]) / A1;
+    const float rA1 = __builtin_amdgcn_rcpf(A1);   // A1 in [1, 31]: about 1 ulp
+    cur.x = (A * cur.x + v[0]) * rA1;
+    cur.y = (A * cur.y + v[1]) * rA1;
+    cur.z = (A * cur.z + v[2]) * rA1;
     cur.w = fminf(A1, 30.f);
     *px = cur;
 }
@@ -1153,9 +1174,10 @@ __device__ __forceinline__ void warp_merge_batch(const int (&zx)[NB], const int 
                     w10 * (float)p[i][2][ch] + w11 * (float)p[i][3][ch];
         float4 c = cur[i];
         const float A = c.w, A1 = A + 1.f;
-        c.x = (A * c.x + v[0]) / A1;
-        c.y = (A * c.y + v[1]) / A1;
-        c.z = (A * c.z + v[2]) / A1;
+        const float rA1 = __builtin_amdgcn_rcpf(A1);   // A1 in [1, 31]: about 1 ulp
+        c.x = (A * c.x + v[0]) * rA1;
+        c.y = (A * c.y + v[1]) * rA1;
+        c.z = (A * c.z + v[2]) * rA1;
         c.w = fminf(A1, 30.f);
         canvas[(size_t)(zy[i] + oy) * cpitch + (zx[i] + ox)] = c;
     }
@@ -1421,7 +1443,7 @@ __device__ __forceinline__ void field_body(
             pzx[i] = zx;
             pzy[i] = zy;
             live[i] = zx < zx0 + w && zy < zy0 + h;
-            pd[i] = blend_displacement(acc[bl][5][r], acc[bl][0][r], acc[bl][1][r], acc[bl][2][r],
+            pd[i] = blend_displacement_field(acc[bl][5][r], acc[bl][0][r], acc[bl][1][r], acc[bl][2][r],
                                        acc[bl][3][r], acc[bl][4][r], fzx, fzy);
             if constexpr (MODE == kModeField) {
                 if (live[i])
@@ -2000,14 +2022,14 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
         const float W = acc[bl][5][r];
         const float C = acc[bl][0][r] + W, S = acc[bl][1][r];
         const float X = acc[bl][2][r], Y = acc[bl][3][r];
-        const float in2 = 1.f / (C * C + S * S), in = sqrtf(in2);
+        const float in2 = __builtin_amdgcn_rcpf(C * C + S * S), in = __builtin_amdgcn_sqrtf(in2);
         const float ch = C * in, sh = S * in;
         const float tx = 2.f * (C * X - S * Y) * in2, ty = 2.f * (S * X + C * Y) * in2;
         const float chc = ch0 * ch - sh0 * sh, shc = sh0 * ch + ch0 * sh;   // R0 R'
         const float ux = (float)zx - pcx, uy = (float)zy - pcy;
         const float ex = -2.f * shc * shc * ux - 2.f * chc * shc * uy + cos0 * tx - sin0 * ty + d0x;
         const float ey = 2.f * chc * shc * ux - 2.f * shc * shc * uy + sin0 * tx + cos0 * ty + d0y;
-        const float sg = sm1 + acc[bl][4][r] / W;
+        const float sg = sm1 + acc[bl][4][r] * __builtin_amdgcn_rcpf(W);
         const float fzx = (float)zx, fzy = (float)zy;
         const float2 d = make_float2(ex + sg * (fzx + ex), ey + sg * (fzy + ey));
         pd[gi] = d;
@@ -2283,7 +2305,7 @@ __device__ __forceinline__ float gelu(float t) {
 // where this error is far below the BF16 rounding step.
 __device__ __forceinline__ float gelu_fast(float t) {
     const float x = fabsf(t) * 0.70710678118654752f;
-    const float u = 1.f / (1.f + 0.3275911f * x);
+    const float u = __builtin_amdgcn_rcpf(1.f + 0.3275911f * x);
     const float poly =
         u * (0.254829592f + u * (-0.284496736f + u * (1.421413741f + u * (-1.453152027f + u * 1.061405429f))));
     const float e = 1.f - poly * fast_exp2(-kLog2e * x * x);   // erf(|t| / sqrt 2)
@@ -3312,6 +3334,10 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     // straight into them
     ok = ok && hipHostMalloc((void **)&m->em_st, 2 * sizeof(DevState), hipHostMallocCoherent) ==
                    hipSuccess;
+    // the slots start at sequence number 0 (the allocator may hand out memory
+    // a freed model used, holding that model's numbers); this model's numbers
+    // start at 1 and only grow, so a slot matches only once its chunk wrote it
+    if (ok) memset(m->em_st, 0, 2 * sizeof(DevState));
     ok = ok && hipHostGetDevicePointer((void **)&m->em_st_dev, m->em_st, 0) == hipSuccess;
     for (int k = 0; ok && k < 2; ++k)
         ok = hipEventCreateWithFlags(&m->em_ev[k], hipEventDisableTiming) == hipSuccess;
