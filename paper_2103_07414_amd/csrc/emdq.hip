@@ -96,6 +96,11 @@ constexpr int kEmChunk = EMDQ_EM_CHUNK; // EM iterations enqueued between stop-f
 #ifndef EMDQ_FUSED_MAX_N
 #define EMDQ_FUSED_MAX_N 2048
 #endif
+// FP32 blend with factor tables: XCD-aware order of the tiles (1) or the
+// launch order (0)
+#ifndef EMDQ_XCD_MAP
+#define EMDQ_XCD_MAP 0
+#endif
 // single-pair EM: the host waits for a chunk's stop flag by polling its
 // sequence number in pinned memory (1) or by an event (0)
 #ifndef EMDQ_EM_POLL
@@ -1231,7 +1236,26 @@ __device__ __forceinline__ void field_body(
     const bool bad = status < 0 || n_in <= 0;
     if (MODE == kModeWarp && bad) return;    // canvas left unchanged
 
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    int tx = tile % tiles_x, ty = tile / tiles_x;
+    if (EMDQ_XCD_MAP && TAB && kTilesPerWg == 1 && tiles_x >= 16 && tile < n_tiles) {
+        // Workgroups go to the 8 XCDs in turn (block b to XCD b % 8): give
+        // XCD x the x-th run of tiles in an order of two column bands, each
+        // row by row, so that its tiles are a compact block and share table
+        // rows in its L2.
+        const int q = n_tiles / 8, r = n_tiles % 8;
+        const int xcd = block < 8 * q ? block % 8 : block - 8 * q;
+        const int slot = block < 8 * q ? block / 8 : q;
+        const int t = xcd * q + min(xcd, r) + slot;
+        const int bw = (tiles_x + 1) / 2, c0 = bw * (n_tiles / tiles_x);
+        if (t < c0) {
+            tx = t % bw;
+            ty = t / bw;
+        } else {
+            const int w1 = tiles_x - bw;
+            tx = bw + (t - c0) % w1;
+            ty = (t - c0) / w1;
+        }
+    }
     const int px0 = zx0 + tx * kTile, py0 = zy0 + ty * kTile * RB;
     const int opitch = filt.opitch > 0 ? filt.opitch : w;
     const int col = lane & 31, half = lane >> 5;

@@ -103,3 +103,23 @@ def test_two_matches_minimum_and_max_n():
     m.field(0, 0, 4, 4, out)
     gy, gx = np.mgrid[0:4, 0:4]
     assert np.abs(out.cpu().numpy() - (np.stack([gx, gy], -1) + 2.0)).max() < 1e-3
+
+
+def test_fresh_models_after_freed_ones_stop_where_the_oracle_stops():
+    """A model's stop-flag slots in pinned memory may be memory a freed model
+    used; its fits must still run to the oracle's iteration count (both EM
+    paths: 1504 and 2807 matches), however many models came and went."""
+    import oracle as O
+    torch = torch_or_skip()
+    E = emdq()
+    pairs = synth.gen_batch(2, seed=3007, with_frame=False)
+    refs = [O.fit(p.src, p.dst, p.cfg.width, p.cfg.height) for p in pairs]
+    dev = [(to_dev(p.src, torch), to_dev(p.dst, torch)) for p in pairs]
+    for cycle in range(4):
+        for p, (s, d), ref in zip(pairs, dev, refs):
+            m = E.Model(p.cfg.n_matches)
+            m.fit(s, d, p.cfg.width, p.cfg.height)
+            r = m.results()
+            m.close()
+            assert (r["status"], r["iters"]) == (ref.status, ref.iters), (cycle, p.cfg.n_matches)
+            assert np.array_equal(r["mask"], ref.mask)
