@@ -106,6 +106,12 @@ constexpr int kEmChunk = EMDQ_EM_CHUNK; // EM iterations enqueued between stop-f
 #ifndef EMDQ_EM_POLL
 #define EMDQ_EM_POLL 1
 #endif
+// single-pair EM: the state of a chunk's end is published by the next
+// chunk's first M-step (1) or by the chunk's last E-step / posterior (0;
+// measured as fast or faster at 2000 matches, slightly slower at 4000)
+#ifndef EMDQ_PUBLISH_MSTEP
+#define EMDQ_PUBLISH_MSTEP 0
+#endif
 // fused single-pair EM: a speculative compaction after every chunk (measured
 // slower: its launches cost more than the host round trip they save)
 #ifndef EMDQ_SPEC_COMPACT
@@ -484,6 +490,8 @@ struct EmFused {
     PostParams pp;
     int nb;                 // workgroups of the EM launches
     int it;                 // this iteration (from 1); posteriors of it - 1
+    DevState *host_copy;    // pinned host memory or null: the state as the launch finds it
+    int seq;                // sequence number published with host_copy
 };
 
 // One wavefront per match i: weights w_j = exp(-alpha |x_j - x_i|^2) p_j.
@@ -554,11 +562,13 @@ __device__ __forceinline__ void mstep_body(
         m_old = F.mask[ic];
         load_chunk(0, min(kMChunk, n));
         const int stop = __atomic_load_n(&st->stop_at, __ATOMIC_RELAXED);
+        if (F.host_copy && block == 0 && threadIdx.x == 0) publish_state(F.host_copy, st, F.seq);
         if (em_stopped(stop, 2 * F.it)) return;
         if (post) run = partial_run(F.part, F.nb, first);
     } else if (kMode == kEmSingle) {
         load_chunk(0, min(kMChunk, n));
         const int status = st->status, done = st->done;
+        if (F.host_copy && block == 0 && threadIdx.x == 0) publish_state(F.host_copy, st, F.seq);
         if (status < 0 || (!final_pass && done)) return;
     }
     if (post) {
@@ -726,9 +736,12 @@ __global__ __launch_bounds__(kEmThreads) void k_mstep(
 
 __global__ __launch_bounds__(kEmThreads) void k_mstep_s(
     const float4 *__restrict__ xy, const float *p, int n, float nal2, double alpha,
-    float4 *__restrict__ q_out, float *__restrict__ s_out, DevState *st, int final_pass) {
-    mstep_body<kEmSingle>(xy, p, n, nal2, alpha, q_out, s_out, st, final_pass, EmFused{},
-                          blockIdx.x);
+    float4 *__restrict__ q_out, float *__restrict__ s_out, DevState *st, int final_pass,
+    DevState *host_copy, int seq) {
+    EmFused F{};
+    F.host_copy = host_copy;
+    F.seq = seq;
+    mstep_body<kEmSingle>(xy, p, n, nal2, alpha, q_out, s_out, st, final_pass, F, blockIdx.x);
 }
 
 // --------------------------------------------------------------- E-step ----
@@ -3473,14 +3486,17 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
     const bool fused = n <= kFusedMaxN;
     // M-step of iteration it (from 1); fused: the posteriors of iteration
     // it - 1 first, when it >= 2
-    auto mstep = [&](int it, int final_pass) {
+    // pub: pinned slot the M-step publishes the state it finds into (the
+    // previous chunk's end), or null
+    auto mstep = [&](int it, int final_pass, DevState *pub = nullptr, int seq = 0) {
         if (fused) {
-            const EmFused F{m->e2, m->part, m->p, m->mask, m->chg, pp, (int)em_blocks, it};
+            const EmFused F{m->e2, m->part, m->p,          m->mask, m->chg, pp,
+                            (int)em_blocks, it, pub, seq};
             hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
                                m->p, n, nal2, alpha, m->q, m->s, m->st, F);
         } else {
             hipLaunchKernelGGL(k_mstep_s, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
-                               m->p, n, nal2, alpha, m->q, m->s, m->st, final_pass);
+                               m->p, n, nal2, alpha, m->q, m->s, m->st, final_pass, pub, seq);
         }
     };
     // EM: iterations are enqueued in chunks; every kernel returns at once
@@ -3501,10 +3517,18 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
         const int seq = ++m->em_seq;
         m->em_slot_seq[k & 1] = seq;
         for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
+            // EMDQ_PUBLISH_MSTEP: the state at the end of chunk k - 1 is
+            // published by the first M-step of chunk k as it starts (its
+            // write completes while that kernel runs); otherwise by the last
+            // E-step / posterior kernel of chunk k as it ends
             const bool last = c + 1 == kEmChunk || enqueued + 1 == prm.max_iter;
-            DevState *slot = last && host_sync ? &m->em_st_dev[k & 1] : nullptr;
+            DevState *slot =
+                last && host_sync && !EMDQ_PUBLISH_MSTEP ? &m->em_st_dev[k & 1] : nullptr;
             const int it = enqueued + 1;
-            mstep(it, 0);
+            if (EMDQ_PUBLISH_MSTEP && host_sync && c == 0 && k > 0)
+                mstep(it, 0, &m->em_st_dev[(k - 1) & 1], m->em_slot_seq[(k - 1) & 1]);
+            else
+                mstep(it, 0);
             if (fused) {
                 const EmStop X{m->chg, slot, prm.max_iter, it, seq};
                 hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
