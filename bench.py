@@ -46,18 +46,18 @@ METRIC = "Mpix/s dense EMDQ field+warp (N=2000); EM iters & px error learned vs 
 PEAK_TFLOPS = {"f32": 157.3, "f16": 2500.0, "bf16": 2500.0}
 # HBM traffic of the production warp call (factor-table kernel + blend kernel)
 # per call, from rocprofv3 FETCH_SIZE + WRITE_SIZE (KiB per dispatch) scaled by
-# the copy-kernel calibration (a 256 MiB copy reads FETCH_SIZE 131,085.2 KiB
-# and WRITE_SIZE 262,144.0 KiB): (57.9 + 43,094.6) x 262,144 / 131,085.2 +
-# (12,609.0 + 18,814.1) x 1.0.  Set to None whenever the kernels change,
+# the copy-kernel calibration (a 256 MiB copy reads FETCH_SIZE 131,085.1 KiB
+# and WRITE_SIZE 262,144.0 KiB): (57.75 + 43,018.16) x 262,144 / 131,085.1 +
+# (12,609.0 + 18,814.06) x 1.0.  Set to None whenever the kernels change,
 # until the counters are taken again.
-TRAFFIC_BYTES = round(((57.9 + 43094.6) * 262144.0 / 131085.2 + (12609.0 + 18814.1)) * 1024)
+TRAFFIC_BYTES = round(((57.75 + 43018.16) * 262144.0 / 131085.1 + (12609.0 + 18814.06)) * 1024)
 # Average duration of the same call in the committed kernel trace of the
 # production command (profiles/k_field_warp_f32_1280x1024_n2000.md): the two
 # kernels' trace averages added, beside the live HIP-event duration the
 # roofline fraction is computed from.
 PROFILE = dict(file="profiles/k_field_warp_f32_1280x1024_n2000.md",
                kernels=["k_field_tables", "k_field<1, 4, 1, true>"],
-               kernel_avg_us=[8.19, 195.57], avg_launch_ms=0.20376)
+               kernel_avg_us=[7.96, 197.43], avg_launch_ms=0.20539)
 WORKLOADS = ("production", "fhd-f32", "fhd-f16", "fhd-bf16", "batch64", "batch64-learned")
 
 
