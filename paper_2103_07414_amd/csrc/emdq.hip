@@ -1674,6 +1674,12 @@ template <int DT> constexpr int kHalfValu = DT == kDtF16 ? 3 : 9;
 #endif
 // MFMAs of a K step issued before the first VALU that waits on its LDS reads
 constexpr int kHalfLead = EMDQ_HALF_LEAD;
+#ifndef EMDQ_HALF_SPREAD
+#define EMDQ_HALF_SPREAD 1  // a K step's LDS reads interleaved with its MFMAs, not issued in a burst
+#endif
+#ifndef EMDQ_HALF_AHEAD
+#define EMDQ_HALF_AHEAD 2   // K steps between a step's LDS operand reads and its MFMAs
+#endif
 template <int DT> struct KB {
     typename HalfT<DT>::V8 a0, a1, b[6];
 };
@@ -1973,6 +1979,53 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_half(
             kload(0, 0, cur);
             kbuild(cur, bcur);
             int buf = 0;
+            if constexpr (EMDQ_HALF_AHEAD == 2) {
+                // Two steps ahead: step t reads the operands of step t + 2,
+                // issues its own MFMAs and forms step t + 1's B operands from
+                // the reads of step t - 1, so no VALU waits on a read issued
+                // in the same step.  Steps 0 and 1 of chunk c + 1 are read
+                // during chunk c (that buffer was complete one barrier early).
+                KOps<DT> nxt;
+                kload(0, 1, cur);
+                for (int c = 0; c < nchunks; ++c) {
+                    const int nbuf = buf == 2 ? 0 : buf + 1;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        kload(s < 2 ? buf : nbuf, (s + 2) & 3, nxt);
+                        kmfma(bcur);
+                        kbuild(cur, bnxt);
+                        if constexpr (EMDQ_HALF_SPREAD) {
+                            // one LDS read after each of the first 8 MFMAs,
+                            // the products spread over all 12
+#pragma unroll
+                            for (int g = 0; g < 12; ++g) {
+                                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                                if (g < 8) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                                __builtin_amdgcn_sched_group_barrier(0x002, DT == kDtF16 ? 2 : 8, 0);
+                            }
+                        } else {
+                            // 8 LDS reads, then one MFMA per kHalfValu VALU
+                            // instructions
+                            __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+                            for (int g = 0; g < 12; ++g) {
+                                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                                __builtin_amdgcn_sched_group_barrier(0x002, kHalfValu<DT>, 0);
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        bcur = bnxt;
+                        cur = nxt;
+                    }
+                    if (c + 2 < nchunks) {
+                        store((c + 2) * kHK, nbuf == 2 ? 0 : nbuf + 1);
+                        if (c + 3 < nchunks) fetch((c + 3) * kHK);
+                    }
+                    __syncthreads();
+                    buf = nbuf;
+                }
+            } else
             for (int c = 0; c < nchunks; ++c) {
                 const int nbuf = buf == 2 ? 0 : buf + 1;
 #pragma unroll
