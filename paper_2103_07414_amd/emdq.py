@@ -80,10 +80,11 @@ def _close_open():
             pass
 
 
-def _release(obj):
+def _release(obj, _finalizing=sys.is_finalizing):
     """__del__ of Model and Batch: release unless the interpreter is
-    already finalising."""
-    if sys.is_finalizing():
+    already finalising.  (What it needs is bound when it is defined: during
+    the interpreter's teardown this module's globals may already be None.)"""
+    if _finalizing():
         return
     try:
         obj.close()
@@ -491,8 +492,8 @@ class Model:
             self.handle = None
         _open.discard(self)
 
-    def __del__(self):
-        _release(self)
+    def __del__(self, _rel=_release):
+        _rel(self)
 
 
 class Batch:
@@ -687,5 +688,5 @@ class Batch:
             self.handle = None
         _open.discard(self)
 
-    def __del__(self):
-        _release(self)
+    def __del__(self, _rel=_release):
+        _rel(self)

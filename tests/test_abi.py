@@ -88,3 +88,27 @@ def test_start_weights_file():
     w = np.load(E.START_WEIGHTS, allow_pickle=False)
     assert w.dtype == np.float32 and w.shape == (E.N_START_WEIGHTS,) == (O.N_WEIGHTS,)
     assert np.isfinite(w).all()
+
+
+def test_objects_alive_at_interpreter_exit_tear_down_quietly():
+    """A model and a batch still referenced when the interpreter exits (here
+    by an object of the main script, with torch imported first, as a bench
+    script does): their destructors run after this module's globals have been
+    cleared and must neither call into HIP nor raise ("Exception ignored in
+    ... __del__")."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch\n"
+        "from paper_2103_07414_amd import emdq as E\n"
+        "class Holder:\n"
+        "    def __init__(self):\n"
+        "        m = E.Model.__new__(E.Model); m.handle = None; m.n = 0\n"
+        "        b = E.Batch.__new__(E.Batch); b.handle = None\n"
+        "        self.objs = [m, b]\n"
+        "h = Holder()\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert "Exception ignored" not in r.stderr, r.stderr
