@@ -385,7 +385,8 @@ def main():
         R.step(stream, events[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    warp_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    warp_times = np.array([a.elapsed_time(b) for a, b in events])
+    warp_ms = float(np.mean(warp_times))
 
     pix = sum(w * h for w, h in sizes)
     flops = sum(12.0 * w * h * r["n_in"] for (w, h), r in zip(sizes, res))
@@ -403,7 +404,9 @@ def main():
                     algorithmic_flops_per_launch=flops, avg_launch_ms=round(warp_ms, 5),
                     duration_source="HIP events recorded around every warp call (both "
                                     "kernels) on the stream it runs on, mean over the "
-                                    "timed steps")
+                                    "timed steps",
+                    warp_ms_p10_median_p90=[round(float(q), 5) for q in
+                                            np.quantile(warp_times, [0.1, 0.5, 0.9])])
     if wl == "production":
         roofline["profile"] = dict(PROFILE, frac_at_profile_duration=round(
             flops / (PROFILE["avg_launch_ms"] * 1e-3) / 1e12 / peak, 4))
