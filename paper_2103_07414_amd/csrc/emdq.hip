@@ -86,6 +86,9 @@ constexpr int field_waves(int rb) { return rb == 1 ? kFieldWaves : 2; }
 #ifndef EMDQ_WARP_BATCH
 #define EMDQ_WARP_BATCH 1   // warp epilogue: a lane's pixels merged with batched loads
 #endif
+#ifndef EMDQ_MSTEP_ONEPASS
+#define EMDQ_MSTEP_ONEPASS 1   // M-step: centred moments from one sweep's raw moments (0: a second sweep)
+#endif
 #ifndef EMDQ_EM_CHUNK
 #define EMDQ_EM_CHUNK 2
 #endif
@@ -496,9 +499,14 @@ struct EmFused {
 
 // One wavefront per match i: weights w_j = exp(-alpha |x_j - x_i|^2) p_j.
 // The workgroup stages the matches in LDS (coalesced, kMChunk at a time) and
-// each wavefront sweeps them from there.  Pass 1: weight sum and weighted
-// centroids, relative to (x_i, y_i).  Pass 2 (weights recomputed): centred
-// cross-covariance terms and spreads, so no moment is formed by cancellation.
+// each wavefront sweeps them from there, accumulating relative to (x_i, y_i)
+// the weight sum, the weighted first moments and the weighted second moments
+// (spreads and the two cross terms of the 2D Procrustes fit); the centred
+// moments follow as raw - S mean^2.  The weights reach about two kernel widths
+// from x_i, so the mean offset is at most about the spread and the subtraction
+// costs at most a few bits; rows whose centred spread is below 1e-2 px^2 of
+// the weight, where it would matter, are refitted in FP64.  (With
+// EMDQ_MSTEP_ONEPASS 0: a second sweep forms the centred moments directly.)
 // Then the closed-form 2D Procrustes fit.  kEmFused: the posterior step first
 // (EmFused); otherwise the posteriors are read from p.
 template <int kMode>
@@ -608,7 +616,7 @@ __device__ __forceinline__ void mstep_body(
     // Fused mode (n <= kMChunk, so the matches are staged once): the first
     // pass keeps every weight in LDS and the second reads it back instead of
     // recomputing it (the same float either way).
-    constexpr bool kKeepW = kMode == kEmFused;
+    constexpr bool kKeepW = kMode == kEmFused && !EMDQ_MSTEP_ONEPASS;
     static_assert(!kKeepW || kFusedMaxN <= kMChunk, "fused M-step stages all matches once");
     __shared__ float s_w[kKeepW ? kRowsPerBlock * kMChunk : 1];
     float *const wrow = s_w + (kKeepW ? (threadIdx.x >> 6) * kMChunk : 0);
@@ -618,6 +626,7 @@ __device__ __forceinline__ void mstep_body(
         return fast_exp2(nal2 * __builtin_fmaf(dxx, dxx, dxy * dxy)) * pj;
     };
     float S = 0.f, Ax = 0.f, Ay = 0.f, Bx = 0.f, By = 0.f;
+    float Pxx = 0.f, Pyy = 0.f, Pa = 0.f, Pb = 0.f;   // raw second moments (one pass)
     for (int c0 = 0; c0 < n; c0 += kMChunk) {
         const int cn = min(kMChunk, n - c0);
         stage(c0, cn);
@@ -626,11 +635,19 @@ __device__ __forceinline__ void mstep_body(
 #pragma clang fp contract(off)
                 const float w = weight(v, pj);
                 if (kKeepW) wrow[t] = w;
+                const float dxx = v.x - me.x, dxy = v.y - me.y;   // x_j - x_i
+                const float dyx = v.z - me.z, dyy = v.w - me.w;   // y_j - y_i
                 S += w;
-                Ax = __builtin_fmaf(w, v.x - me.x, Ax);
-                Ay = __builtin_fmaf(w, v.y - me.y, Ay);
-                Bx = __builtin_fmaf(w, v.z - me.z, Bx);           // y_j - y_i
-                By = __builtin_fmaf(w, v.w - me.w, By);
+                Ax = __builtin_fmaf(w, dxx, Ax);
+                Ay = __builtin_fmaf(w, dxy, Ay);
+                Bx = __builtin_fmaf(w, dyx, Bx);
+                By = __builtin_fmaf(w, dyy, By);
+                if constexpr (EMDQ_MSTEP_ONEPASS) {
+                    Pxx = __builtin_fmaf(w, __builtin_fmaf(dxx, dxx, dxy * dxy), Pxx);
+                    Pyy = __builtin_fmaf(w, __builtin_fmaf(dyx, dyx, dyy * dyy), Pyy);
+                    Pa = __builtin_fmaf(w, __builtin_fmaf(dyx, dxx, dyy * dxy), Pa);
+                    Pb = __builtin_fmaf(w, __builtin_fmaf(dyy, dxx, -(dyx * dxy)), Pb);
+                }
             };
             int t = lane;
             for (; t + 3 * kWave < cn; t += 4 * kWave) {   // 4 LDS reads in flight
@@ -660,7 +677,20 @@ __device__ __forceinline__ void mstep_body(
     }
     // weighted centroids in absolute coordinates
     const float cxx = me.x + mx, cxy = me.y + my, cyx = me.z + nx, cyy = me.w + ny;
-    for (int c0 = 0; c0 < n; c0 += kMChunk) {
+    if constexpr (EMDQ_MSTEP_ONEPASS) {
+        // centred moments from the raw ones: sum w (d - m)(e - n) = P - S m n
+        Pxx = wave_sum(Pxx);
+        Pyy = wave_sum(Pyy);
+        Pa = wave_sum(Pa);
+        Pb = wave_sum(Pb);
+        if (have_w) {
+            vx = Pxx - S * __builtin_fmaf(mx, mx, my * my);
+            vy = Pyy - S * __builtin_fmaf(nx, nx, ny * ny);
+            a = Pa - S * __builtin_fmaf(nx, mx, ny * my);
+            b = Pb - S * __builtin_fmaf(ny, mx, -(nx * my));
+        }
+    }
+    for (int c0 = 0; EMDQ_MSTEP_ONEPASS == 0 && c0 < n; c0 += kMChunk) {
         const int cn = min(kMChunk, n - c0);
         if (!resident) stage(c0, cn);
         if (active && have_w) {
@@ -690,10 +720,12 @@ __device__ __forceinline__ void mstep_body(
         }
     }
     if (!active) return;
-    vx = wave_sum(vx);
-    vy = wave_sum(vy);
-    a = wave_sum(a);
-    b = wave_sum(b);
+    if constexpr (!EMDQ_MSTEP_ONEPASS) {
+        vx = wave_sum(vx);
+        vy = wave_sum(vy);
+        a = wave_sum(a);
+        b = wave_sum(b);
+    }
 
     float scale;
     float4 q;
