@@ -543,11 +543,21 @@ __device__ __forceinline__ void mstep_body(
         }
     };
     PostCoef pc{};
+    // fused mode: whether a mask bit of the workgroup's rows changed, OR-ed
+    // over the workgroup by the first staging barrier
+    int changed = 0;
+    bool first_stage = true;
     auto store_chunk = [&](int cn) {
         float pv[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) pv[k] = post ? post_p(r[k], pc) : r[k];
-        __syncthreads();
+        if (kMode == kEmFused && first_stage) {
+            const int any = __syncthreads_or(changed);
+            if (post && threadIdx.x == 0) F.chg[block] = any;
+        } else {
+            __syncthreads();
+        }
+        first_stage = false;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int t = threadIdx.x + k * kEmThreads;
@@ -593,7 +603,6 @@ __device__ __forceinline__ void mstep_body(
             st->sigma2 = (float)sigma2;
             st->gamma = (float)pc.gamma;
         }
-        int changed = 0;
         if (active && lane == 0) {
             const float pn = post_p(e2_own, pc);
             const uint8_t m = pn > F.pp.p_thresh ? 1 : 0;
@@ -601,8 +610,6 @@ __device__ __forceinline__ void mstep_body(
             F.p_out[i] = pn;
             F.mask[i] = m;
         }
-        changed = __syncthreads_or(changed);
-        if (threadIdx.x == 0) F.chg[block] = changed;
     }
     auto post_of = [&](int j) { return post ? post_p(F.e2[j], pc) : p[j]; };
     const bool resident = n <= kMChunk;   // one staging serves both passes
