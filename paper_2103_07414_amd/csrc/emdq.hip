@@ -615,9 +615,12 @@ __device__ __forceinline__ void mstep_body(
     const bool resident = n <= kMChunk;   // one staging serves both passes
     bool preloaded = kMode != kEmBatch;   // the first chunk's registers are loaded already
     auto stage = [&](int c0, int cn) {
-        if (preloaded) preloaded = false;
-        else load_chunk(c0, cn);
+        if (!preloaded) load_chunk(c0, cn);
         store_chunk(cn);
+        // the next chunk's loads go out now (its registers are free once
+        // this chunk is in LDS) and land during this chunk's sweep
+        if (c0 + kMChunk < n) load_chunk(c0 + kMChunk, min(kMChunk, n - c0 - kMChunk));
+        preloaded = true;
     };
 
     // Fused mode (n <= kMChunk, so the matches are staged once): the first
@@ -697,6 +700,7 @@ __device__ __forceinline__ void mstep_body(
             b = Pb - S * __builtin_fmaf(ny, mx, -(nx * my));
         }
     }
+    if (!resident) preloaded = false;   // the second sweep restages from the first chunk
     for (int c0 = 0; EMDQ_MSTEP_ONEPASS == 0 && c0 < n; c0 += kMChunk) {
         const int cn = min(kMChunk, n - c0);
         if (!resident) stage(c0, cn);
@@ -891,9 +895,12 @@ __device__ __forceinline__ void estep_body(
     float W = 0.f, Gd = 0.f, Cd = 0.f, Sn = 0.f, X = 0.f, Y = 0.f;
     for (int c0 = 0; c0 < n; c0 += kEChunk) {
         const int cn = min(kEChunk, n - c0);
-        if (preloaded) preloaded = false;
-        else load_chunk(c0, cn);
+        if (!preloaded) load_chunk(c0, cn);
         store_chunk(cn);
+        // the next chunk's loads go out now (its registers are free once
+        // this chunk is in LDS) and land during this chunk's sweep
+        if (c0 + kEChunk < n) load_chunk(c0 + kEChunk, min(kEChunk, n - c0 - kEChunk));
+        preloaded = true;
         if (active) {
             auto acc1 = [&](const float4 &v, const float2 &ps, const float4 &qj) {
 #pragma clang fp contract(off)
