@@ -202,17 +202,20 @@ __global__ void k_reset(DevState *st) {
     if (threadIdx.x == 0) reset_state(st);
 }
 
-// xy[i] = (src_i, dst_i); p = 1, mask = 1; a non-finite coordinate sets the
-// status to ENONFINITE (every writer stores the same value).
+// xy[i] = (src_i, dst_i); p = 1, mask = 1; cent[i] = 0 (the M-step's
+// moment origin starts at the match itself); a non-finite coordinate sets
+// the status to ENONFINITE (every writer stores the same value).
 __device__ __forceinline__ void load_body(const float2 *__restrict__ src, const float2 *__restrict__ dst, int n,
                        float4 *__restrict__ xy, float *__restrict__ p,
-                       uint8_t *__restrict__ mask, DevState *st, int block) {
+                       uint8_t *__restrict__ mask, float4 *__restrict__ cent, DevState *st,
+                       int block) {
     int i = block * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float2 a = src[i], b = dst[i];
     xy[i] = make_float4(a.x, a.y, b.x, b.y);
     p[i] = 1.f;
     mask[i] = 1;
+    cent[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (!finite2(a) || !finite2(b)) {
         atomicMin(&st->status, (int)EMDQ_ENONFINITE);
         atomicExch(&st->done, 1);
@@ -222,8 +225,8 @@ __device__ __forceinline__ void load_body(const float2 *__restrict__ src, const 
 
 __global__ void k_load(const float2 *__restrict__ src, const float2 *__restrict__ dst, int n,
                        float4 *__restrict__ xy, float *__restrict__ p,
-                       uint8_t *__restrict__ mask, DevState *st) {
-    load_body(src, dst, n, xy, p, mask, st, blockIdx.x);
+                       uint8_t *__restrict__ mask, float4 *__restrict__ cent, DevState *st) {
+    load_body(src, dst, n, xy, p, mask, cent, st, blockIdx.x);
 }
 
 // ------------------------------------------------- blend evaluation ----
@@ -499,21 +502,23 @@ struct EmFused {
 
 // One wavefront per match i: weights w_j = exp(-alpha |x_j - x_i|^2) p_j.
 // The workgroup stages the matches in LDS (coalesced, kMChunk at a time) and
-// each wavefront sweeps them from there, accumulating relative to (x_i, y_i)
-// the weight sum, the weighted first moments and the weighted second moments
-// (spreads and the two cross terms of the 2D Procrustes fit); the centred
-// moments follow as raw - S mean^2.  The weights reach about two kernel widths
-// from x_i, so the mean offset is at most about the spread and the subtraction
-// costs at most a few bits; rows whose centred spread is below 1e-2 px^2 of
-// the weight, where it would matter, are refitted in FP64.  (With
-// EMDQ_MSTEP_ONEPASS 0: a second sweep forms the centred moments directly.)
+// each wavefront sweeps them from there once, accumulating the weight sum and
+// the weighted first and second moments (spreads and the two cross terms of
+// the 2D Procrustes fit) relative to an origin o; the centred moments follow
+// as raw - S (mean - o)^2.  o is the match shifted by its weighted centroids
+// of the previous M-step (cent, zeroed when a fit starts), so mean - o is the
+// centroid's move in one iteration and the subtraction loses nothing that
+// matters (measured: fits as close to the FP64 oracle as with a second sweep;
+// with o = x_i, matches whose neighbours lie far to one side lost up to 50x).
+// Rows whose centred spread is below 1e-2 px^2 of the weight are refitted in
+// FP64.  (EMDQ_MSTEP_ONEPASS 0: a second sweep forms the centred moments.)
 // Then the closed-form 2D Procrustes fit.  kEmFused: the posterior step first
 // (EmFused); otherwise the posteriors are read from p.
 template <int kMode>
 __device__ __forceinline__ void mstep_body(
     const float4 *__restrict__ xy, const float *p, int n, float nal2,
     double alpha, float4 *__restrict__ q_out, float *__restrict__ s_out,
-    DevState *st, int final_pass, const EmFused &F, int block) {
+    float4 *__restrict__ cent, DevState *st, int final_pass, const EmFused &F, int block) {
 #pragma clang fp contract(off)
     __shared__ float4 s_xy[kMChunk];
     __shared__ float s_p[kMChunk];
@@ -570,6 +575,11 @@ __device__ __forceinline__ void mstep_body(
     // last, so that one wait covers them all); the posterior loads are unused
     // when it = 1
     const float4 me = active ? xy[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // moment origin: the match shifted by its weighted centroids of the
+    // previous M-step (zero at the first), so the centred moments lose
+    // nothing to cancellation
+    const float4 sh = EMDQ_MSTEP_ONEPASS && active ? cent[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 o = make_float4(me.x + sh.x, me.y + sh.y, me.z + sh.z, me.w + sh.w);
     double2 run = make_double2(0.0, 0.0);
     float e2_own = 0.f;
     uint8_t m_old = 0;
@@ -645,8 +655,8 @@ __device__ __forceinline__ void mstep_body(
 #pragma clang fp contract(off)
                 const float w = weight(v, pj);
                 if (kKeepW) wrow[t] = w;
-                const float dxx = v.x - me.x, dxy = v.y - me.y;   // x_j - x_i
-                const float dyx = v.z - me.z, dyy = v.w - me.w;   // y_j - y_i
+                const float dxx = v.x - o.x, dxy = v.y - o.y;   // x_j - origin
+                const float dyx = v.z - o.z, dyy = v.w - o.w;   // y_j - origin
                 S += w;
                 Ax = __builtin_fmaf(w, dxx, Ax);
                 Ay = __builtin_fmaf(w, dxy, Ay);
@@ -686,7 +696,7 @@ __device__ __forceinline__ void mstep_body(
         mx = Ax / S; my = Ay / S; nx = Bx / S; ny = By / S;
     }
     // weighted centroids in absolute coordinates
-    const float cxx = me.x + mx, cxy = me.y + my, cyx = me.z + nx, cyy = me.w + ny;
+    const float cxx = o.x + mx, cxy = o.y + my, cyx = o.z + nx, cyy = o.w + ny;
     if constexpr (EMDQ_MSTEP_ONEPASS) {
         // centred moments from the raw ones: sum w (d - m)(e - n) = P - S m n
         Pxx = wave_sum(Pxx);
@@ -759,8 +769,8 @@ __device__ __forceinline__ void mstep_body(
             sh = hy / hn;
         }
         scale = sqrtf(vy / vx);
-        const float cx = me.x + mx, cy = me.y + my;     // weighted centroid of x
-        const float gx = me.z + nx, gy = me.w + ny;     // weighted centroid of y
+        const float cx = o.x + mx, cy = o.y + my;       // weighted centroid of x
+        const float gx = o.z + nx, gy = o.w + ny;       // weighted centroid of y
         const float tx = gx / scale - __builtin_fmaf(ct, cx, -(stt * cy));
         const float ty = gy / scale - __builtin_fmaf(stt, cx, ct * cy);
         q = dq_make(ch, sh, tx, ty);
@@ -768,23 +778,27 @@ __device__ __forceinline__ void mstep_body(
     if (lane == 0) {
         q_out[i] = q;
         s_out[i] = scale;
+        if (EMDQ_MSTEP_ONEPASS)   // the next M-step's moment origin
+            cent[i] = make_float4(sh.x + mx, sh.y + my, sh.z + nx, sh.w + ny);
     }
 }
 
 __global__ __launch_bounds__(kEmThreads) void k_mstep(
     const float4 *__restrict__ xy, const float *p, int n, float nal2, double alpha,
-    float4 *__restrict__ q_out, float *__restrict__ s_out, DevState *st, EmFused F) {
-    mstep_body<kEmFused>(xy, p, n, nal2, alpha, q_out, s_out, st, 0, F, blockIdx.x);
+    float4 *__restrict__ q_out, float *__restrict__ s_out, float4 *__restrict__ cent,
+    DevState *st, EmFused F) {
+    mstep_body<kEmFused>(xy, p, n, nal2, alpha, q_out, s_out, cent, st, 0, F, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kEmThreads) void k_mstep_s(
     const float4 *__restrict__ xy, const float *p, int n, float nal2, double alpha,
-    float4 *__restrict__ q_out, float *__restrict__ s_out, DevState *st, int final_pass,
-    DevState *host_copy, int seq) {
+    float4 *__restrict__ q_out, float *__restrict__ s_out, float4 *__restrict__ cent,
+    DevState *st, int final_pass, DevState *host_copy, int seq) {
     EmFused F{};
     F.host_copy = host_copy;
     F.seq = seq;
-    mstep_body<kEmSingle>(xy, p, n, nal2, alpha, q_out, s_out, st, final_pass, F, blockIdx.x);
+    mstep_body<kEmSingle>(xy, p, n, nal2, alpha, q_out, s_out, cent, st, final_pass, F,
+                          blockIdx.x);
 }
 
 // --------------------------------------------------------------- E-step ----
@@ -2907,7 +2921,8 @@ __global__ __launch_bounds__(kStartThreads) void k_start_b(const StartJob *__res
 __device__ __forceinline__ void load_from_body(
     const float2 *__restrict__ src, const float2 *__restrict__ dst,
     const float *__restrict__ init_p, int n, float p_thresh, float4 *__restrict__ xy,
-    float *__restrict__ p, uint8_t *__restrict__ mask, DevState *st, int block) {
+    float *__restrict__ p, uint8_t *__restrict__ mask, float4 *__restrict__ cent, DevState *st,
+    int block) {
     const int i = block * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float2 a = src[i], b = dst[i];
@@ -2915,6 +2930,7 @@ __device__ __forceinline__ void load_from_body(
     xy[i] = make_float4(a.x, a.y, b.x, b.y);
     p[i] = pi;
     mask[i] = pi > p_thresh ? 1 : 0;
+    cent[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (!finite2(a) || !finite2(b) || !__builtin_isfinite(pi)) {
         atomicMin(&st->status, (int)EMDQ_ENONFINITE);
         atomicExch(&st->done, 1);
@@ -2925,8 +2941,8 @@ __device__ __forceinline__ void load_from_body(
 __global__ void k_load_from(const float2 *__restrict__ src, const float2 *__restrict__ dst,
                             const float *__restrict__ init_p, int n, float p_thresh,
                             float4 *__restrict__ xy, float *__restrict__ p,
-                            uint8_t *__restrict__ mask, DevState *st) {
-    load_from_body(src, dst, init_p, n, p_thresh, xy, p, mask, st, blockIdx.x);
+                            uint8_t *__restrict__ mask, float4 *__restrict__ cent, DevState *st) {
+    load_from_body(src, dst, init_p, n, p_thresh, xy, p, mask, cent, st, blockIdx.x);
 }
 
 
@@ -3104,6 +3120,7 @@ struct EmJob {
     double2 *part;       // E-step sums per workgroup
     float4 *q;
     float *s;
+    float4 *cent;        // M-step moment origins (relative to each match)
     float4 *packed;
     float *xs, *ys;
     DevState *st;
@@ -3133,17 +3150,17 @@ __global__ void k_load_b(const EmJob *__restrict__ jobs, float p_thresh) {
     const EmJob &J = jobs[blockIdx.y];
     if ((int)blockIdx.x * (int)blockDim.x >= J.n) return;
     if (J.init_p)
-        load_from_body(J.src, J.dst, J.init_p, J.n, p_thresh, J.xy, J.p, J.mask, J.st,
-                       blockIdx.x);
+        load_from_body(J.src, J.dst, J.init_p, J.n, p_thresh, J.xy, J.p, J.mask, J.cent,
+                       J.st, blockIdx.x);
     else
-        load_body(J.src, J.dst, J.n, J.xy, J.p, J.mask, J.st, blockIdx.x);
+        load_body(J.src, J.dst, J.n, J.xy, J.p, J.mask, J.cent, J.st, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kEmThreads) void k_mstep_b(const EmJob *__restrict__ jobs,
                                                         int final_pass) {
     const EmJob &J = jobs[blockIdx.y];
     if ((int)blockIdx.x >= J.blocks) return;
-    mstep_body<kEmBatch>(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.st, final_pass,
+    mstep_body<kEmBatch>(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.cent, J.st, final_pass,
                          EmFused{}, blockIdx.x);
 }
 
@@ -3232,6 +3249,7 @@ struct emdq_model_s {
     int *chg = nullptr;        // EM: per M-step workgroup, a mask bit changed
     float4 *q = nullptr;
     float *s = nullptr;
+    float4 *cent = nullptr;  // EM: each match's M-step moment origin (previous centroids)
     float4 *packed = nullptr;
     float *xs = nullptr;     // inlier coordinates, SoA, padded by one chunk
     float *ys = nullptr;
@@ -3458,6 +3476,7 @@ emdq_status emdq_model_create(int n_max, emdq_model *out) {
     ok = ok && hipMalloc((void **)&m->chg, nb * sizeof(int)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->q, n * sizeof(float4)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->s, n * sizeof(float)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&m->cent, n * sizeof(float4)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->packed, 2 * n * sizeof(float4)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->xs, (n + kHK) * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc((void **)&m->ys, (n + kHK) * sizeof(float)) == hipSuccess;
@@ -3509,6 +3528,7 @@ void emdq_model_free(emdq_model m) {
     (void)hipFree(m->part);
     (void)hipFree(m->chg);
     (void)hipFree(m->q);
+    (void)hipFree(m->cent);
     (void)hipFree(m->s);
     (void)hipFree(m->packed);
     (void)hipFree(m->xs);
@@ -3571,11 +3591,11 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
     if (init_p)
         hipLaunchKernelGGL(k_load_from, dim3((n + 255) / 256), dim3(256), 0, stream,
                            (const float2 *)src_xy, (const float2 *)dst_xy, init_p, n,
-                           prm.p_thresh, m->xy, m->p, m->mask, m->st);
+                           prm.p_thresh, m->xy, m->p, m->mask, m->cent, m->st);
     else
         hipLaunchKernelGGL(k_load, dim3((n + 255) / 256), dim3(256), 0, stream,
                            (const float2 *)src_xy, (const float2 *)dst_xy, n, m->xy, m->p,
-                           m->mask, m->st);
+                           m->mask, m->cent, m->st);
     if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
     const PostParams pp{u, (double)prm.sigma2_min, (double)prm.gamma_min, (double)prm.gamma_max,
                         prm.p_thresh, prm.max_iter};
@@ -3592,10 +3612,11 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
             const EmFused F{m->e2, m->part, m->p,          m->mask, m->chg, pp,
                             (int)em_blocks, it, pub, seq};
             hipLaunchKernelGGL(k_mstep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
-                               m->p, n, nal2, alpha, m->q, m->s, m->st, F);
+                               m->p, n, nal2, alpha, m->q, m->s, m->cent, m->st, F);
         } else {
             hipLaunchKernelGGL(k_mstep_s, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
-                               m->p, n, nal2, alpha, m->q, m->s, m->st, final_pass, pub, seq);
+                               m->p, n, nal2, alpha, m->q, m->s, m->cent, m->st, final_pass,
+                               pub, seq);
         }
     };
     // EM: iterations are enqueued in chunks; every kernel returns at once
@@ -4176,6 +4197,7 @@ emdq_status fill_em_jobs(emdq_batch b, EmJob *jobs, int n_pairs, const emdq_mode
         J.part = m->part;
         J.q = m->q;
         J.s = m->s;
+        J.cent = m->cent;
         J.packed = m->packed;
         J.xs = m->xs;
         J.ys = m->ys;
@@ -4580,7 +4602,8 @@ constexpr size_t kStPart = kStE2 + round256(kStN * sizeof(float));
 constexpr size_t kStChg = kStPart + round256(kStNb * sizeof(double2));
 constexpr size_t kStQ = kStChg + round256(kStNb * sizeof(int));
 constexpr size_t kStS = kStQ + round256(kStN * sizeof(float4));
-constexpr size_t kStPacked = kStS + round256(kStN * sizeof(float));
+constexpr size_t kStCent = kStS + round256(kStN * sizeof(float));
+constexpr size_t kStPacked = kStCent + round256(kStN * sizeof(float4));
 constexpr size_t kStXs = kStPacked + round256(2 * kStN * sizeof(float4));
 constexpr size_t kStYs = kStXs + round256((kStN + kHK) * sizeof(float));
 constexpr size_t kStSt = kStYs + round256((kStN + kHK) * sizeof(float));
@@ -4620,6 +4643,7 @@ emdq_status static_model(emdq_model *out) {
         m.chg = (int *)(ptr + kStChg);
         m.q = (float4 *)(ptr + kStQ);
         m.s = (float *)(ptr + kStS);
+        m.cent = (float4 *)(ptr + kStCent);
         m.packed = (float4 *)(ptr + kStPacked);
         m.xs = (float *)(ptr + kStXs);
         m.ys = (float *)(ptr + kStYs);
