@@ -56,6 +56,15 @@ def test_fit_parity_production(pair_id):
     _fit_parity(2, pair_id, torch)
 
 
+@pytest.mark.parametrize("cfg", [4, 5])
+def test_fit_parity_1920x1080(cfg):
+    """N = 4000 and 5000 (multi-chunk M-step sweeps, config 5 with 40 %
+    outliers): the same bar as at production size; the per-fit prediction
+    is where a loss of precision in the M-step's moments shows first."""
+    torch = torch_or_skip()
+    _fit_parity(cfg, 1, torch)
+
+
 @pytest.mark.parametrize("pair_id", [1, 2])
 def test_field_parity_small_whole_roi(pair_id):
     """Fit + field on the GPU vs fit + field in the oracle, every pixel,
