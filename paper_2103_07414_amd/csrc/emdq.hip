@@ -136,6 +136,7 @@ struct DevState {
     float gamma;
     int stop_at;     // single-pair fit: launch that ended the EM (em_stopped), 0 = running
     int packed;      // the inliers are packed (speculative compaction done)
+    int fitted;      // batched fit: the final M-step of the stopped pair has run
     int seq;         // host copies only: sequence number of the publishing launch
 };
 
@@ -185,6 +186,7 @@ __device__ __forceinline__ void reset_state(DevState *st) {
     st->gamma = 0.f;
     st->stop_at = 0;
     st->packed = 0;
+    st->fitted = 0;
     st->seq = 0;
 }
 
@@ -523,8 +525,10 @@ __device__ __forceinline__ void mstep_body(
     __shared__ float4 s_xy[kMChunk];
     __shared__ float s_p[kMChunk];
     if (kMode == kEmBatch) {
-        if (st->status < 0) return;
-        if (!final_pass && st->done) return;
+        // a stopped pair's final fit is the first M-step after its stop (the
+        // same inputs as a pass after the last iteration, so the same bits);
+        // the posterior step that follows it marks the pair fitted
+        if (st->status < 0 || st->fitted) return;
     }
     const int lane = threadIdx.x & (kWave - 1);
     const int i = block * kRowsPerBlock + (threadIdx.x >> 6);
@@ -3156,25 +3160,34 @@ __global__ void k_load_b(const EmJob *__restrict__ jobs, float p_thresh) {
         load_body(J.src, J.dst, J.n, J.xy, J.p, J.mask, J.cent, J.st, blockIdx.x);
 }
 
+// The per-iteration batch kernels take blockIdx.y (x for the posterior step)
+// as an index into act, the pairs still running, or as the pair when act is
+// null.
 __global__ __launch_bounds__(kEmThreads) void k_mstep_b(const EmJob *__restrict__ jobs,
-                                                        int final_pass) {
-    const EmJob &J = jobs[blockIdx.y];
+                                                        const int *__restrict__ act) {
+    const EmJob &J = jobs[act ? act[blockIdx.y] : (int)blockIdx.y];
     if ((int)blockIdx.x >= J.blocks) return;
-    mstep_body<kEmBatch>(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.cent, J.st, final_pass,
-                         EmFused{}, blockIdx.x);
+    mstep_body<kEmBatch>(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.cent, J.st, 1, EmFused{},
+                         blockIdx.x);
 }
 
-__global__ __launch_bounds__(kEmThreads) void k_estep_b(const EmJob *__restrict__ jobs) {
-    const EmJob &J = jobs[blockIdx.y];
+__global__ __launch_bounds__(kEmThreads) void k_estep_b(const EmJob *__restrict__ jobs,
+                                                        const int *__restrict__ act) {
+    const EmJob &J = jobs[act ? act[blockIdx.y] : (int)blockIdx.y];
     if ((int)blockIdx.x >= J.blocks) return;
     estep_body<kEmBatch>(J.xy, J.p, J.q, J.s, J.n, J.nal2, J.e2, J.part, J.blocks, J.st,
                          EmStop{}, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kPostThreads) void k_posterior_b(
-    const EmJob *__restrict__ jobs, double sigma2_min, double gamma_min, double gamma_max,
-    float p_thresh, int max_iter) {
-    const EmJob &J = jobs[blockIdx.x];
+    const EmJob *__restrict__ jobs, const int *__restrict__ act, double sigma2_min,
+    double gamma_min, double gamma_max, float p_thresh, int max_iter) {
+    const EmJob &J = jobs[act ? act[blockIdx.x] : (int)blockIdx.x];
+    // a pair found stopped has had its final fit in this iteration's M-step
+    if (J.st->status >= 0 && J.st->done) {
+        if (threadIdx.x == 0) J.st->fitted = 1;
+        return;
+    }
     const PostParams pp{J.u, sigma2_min, gamma_min, gamma_max, p_thresh, max_iter};
     posterior_body(J.p, J.e2, J.mask, J.n, J.part, J.blocks, pp, J.st, nullptr, 0);
 }
@@ -3926,6 +3939,8 @@ struct emdq_batch_s {
     long long prep_blocks = 0;
     DevState *states = nullptr;      // device, gathered per chunk
     DevState *host_states = nullptr; // pinned, two sets (read while the EM runs on)
+    int *act = nullptr;              // device: the pairs still running
+    int *host_act = nullptr;         // pinned, two sets: their uploads
     hipEvent_t em_ev[2] = {};
     static constexpr int kSlots = 4; // pinned staging ring for the job tables
     void *stage[kSlots] = {};
@@ -4216,10 +4231,12 @@ emdq_status fill_em_jobs(emdq_batch b, EmJob *jobs, int n_pairs, const emdq_mode
 
 // Enqueues the batched EM of the job table `jobs` (device).  host_stop: the
 // host reads all pairs' stop flags between chunks of iterations and stops
-// enqueuing once every pair has stopped; otherwise the whole budget of
-// max_iter iterations is enqueued with no copy and no host synchronisation
-// (the kernels of a stopped pair return at entry, so the results are the
-// same bits), which a hipGraph can capture.
+// enqueuing once every pair has stopped; from the same flags it launches the
+// next chunk's kernels over the pairs they show neither fitted nor failed
+// (the kernels of the others would return at entry).  Otherwise the whole budget
+// of max_iter iterations is enqueued over all pairs with no copy and no host
+// synchronisation (the kernels of a stopped pair return at entry, so the
+// results are the same bits), which a hipGraph can capture.
 emdq_status enqueue_batch_em(emdq_batch b, const EmJob *jobs, int n_pairs,
                              const BatchEmShape &shape, const emdq_params &prm,
                              hipStream_t stream, bool host_stop) {
@@ -4228,19 +4245,21 @@ emdq_status enqueue_batch_em(emdq_batch b, const EmJob *jobs, int n_pairs,
     hipLaunchKernelGGL(k_load_b, dim3((unsigned)((shape.max_n + 255) / 256), P), dim3(256), 0,
                        stream, jobs, prm.p_thresh);
     if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
-    auto mstep_b = [&](int final_pass) {
-        hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)shape.max_blocks, P), dim3(kEmThreads), 0,
-                           stream, jobs, final_pass);
+    const int *act = nullptr;   // null: every pair
+    unsigned n_act = P;
+    auto mstep_b = [&]() {
+        hipLaunchKernelGGL(k_mstep_b, dim3((unsigned)shape.max_blocks, n_act), dim3(kEmThreads),
+                           0, stream, jobs, act);
     };
     int enqueued = 0;
     for (int k = 0;; ++k) {
         for (int c = 0; (c < kEmChunk || !host_stop) && enqueued < prm.max_iter;
              ++c, ++enqueued) {
-            mstep_b(0);
-            hipLaunchKernelGGL(k_estep_b, dim3((unsigned)shape.max_blocks, P), dim3(kEmThreads),
-                               0, stream, jobs);
-            hipLaunchKernelGGL(k_posterior_b, dim3(P), dim3(kPostThreads), 0, stream, jobs,
-                               (double)prm.sigma2_min, (double)prm.gamma_min,
+            mstep_b();
+            hipLaunchKernelGGL(k_estep_b, dim3((unsigned)shape.max_blocks, n_act),
+                               dim3(kEmThreads), 0, stream, jobs, act);
+            hipLaunchKernelGGL(k_posterior_b, dim3(n_act), dim3(kPostThreads), 0, stream, jobs,
+                               act, (double)prm.sigma2_min, (double)prm.gamma_min,
                                (double)prm.gamma_max, prm.p_thresh, prm.max_iter);
         }
         if (check_launch() != EMDQ_OK) return EMDQ_EHIP;
@@ -4258,10 +4277,23 @@ emdq_status enqueue_batch_em(emdq_batch b, const EmJob *jobs, int n_pairs,
             bool all = true;
             for (int i = 0; i < n_pairs; ++i) all = all && (prev[i].done || prev[i].status < 0);
             if (all) break;
+            // the pairs not yet fitted; the upload from this set of the
+            // pinned list went out before chunk k - 1, which has completed
+            int *list = b->host_act + (size_t)(k & 1) * b->max_pairs;
+            unsigned m = 0;
+            for (int i = 0; i < n_pairs; ++i)
+                if (prev[i].status >= 0 && !prev[i].fitted) list[m++] = i;
+            if (m > 0 && m < n_act) {
+                EMDQ_HIP(hipMemcpyAsync(b->act, list, sizeof(int) * m, hipMemcpyHostToDevice,
+                                        stream));
+                act = b->act;
+                n_act = m;
+            }
         }
         if (enqueued >= prm.max_iter) break;
     }
-    mstep_b(1);
+    // the final fit of the pairs that have not had it
+    mstep_b();
     hipLaunchKernelGGL(k_compact_b, dim3(P), dim3(kCompactThreads), 0, stream, jobs);
     return check_launch();
 }
@@ -4317,6 +4349,9 @@ emdq_status emdq_batch_create(int max_pairs, emdq_batch *out) {
     ok = ok && hipMalloc((void **)&b->states, 2 * n * sizeof(DevState)) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&b->host_states, 2 * n * sizeof(DevState),
                              hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b->act, n * sizeof(int)) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->host_act, 2 * n * sizeof(int),
+                             hipHostMallocDefault) == hipSuccess;
     for (int k = 0; ok && k < 2; ++k)
         ok = hipEventCreateWithFlags(&b->em_ev[k], hipEventDisableTiming) == hipSuccess;
     for (int k = 0; ok && k < emdq_batch_s::kSlots; ++k) {
@@ -4351,6 +4386,8 @@ void emdq_batch_free(emdq_batch b) {
     (void)hipFree(b->step_field);
     (void)hipFree(b->states);
     if (b->host_states) (void)hipHostFree(b->host_states);
+    (void)hipFree(b->act);
+    if (b->host_act) (void)hipHostFree(b->host_act);
     for (int k = 0; k < 2; ++k)
         if (b->em_ev[k]) (void)hipEventDestroy(b->em_ev[k]);
     delete b;
