@@ -46,6 +46,17 @@ constexpr int kWave = 64;
 constexpr int kRowsPerBlock = 8;        // EM kernels: one wavefront per match
 template <int V> struct IntTag { static constexpr int value = V; };
 constexpr int kEmThreads = kWave * kRowsPerBlock;
+// E-step: match rows per wavefront (each staged match is read from LDS once
+// for all of them), single pair and batch; the same bits either way
+#ifndef EMDQ_E_ROWS
+#define EMDQ_E_ROWS 1
+#endif
+#ifndef EMDQ_E_ROWS_BATCH
+#define EMDQ_E_ROWS_BATCH 2
+#endif
+constexpr int e_threads(int rows) { return kWave * kRowsPerBlock / rows; }
+constexpr int kEThreads = e_threads(EMDQ_E_ROWS);         // single-pair E-step workgroup
+constexpr int kEThreadsB = e_threads(EMDQ_E_ROWS_BATCH);  // batched E-step workgroup
 #ifndef EMDQ_MCHUNK
 #define EMDQ_MCHUNK 2048
 #endif
@@ -820,29 +831,35 @@ struct EmStop {
 // Blend of all fits at match i with weights exp(-alpha d^2) p_j (Eqs. (2)-(3)),
 // normalisation, prediction y_hat = s (R x_i + t) (Eq. (1)), residual e_i^2.
 // The workgroup also leaves (sum p_i, sum p_i e_i^2) over its rows, in row
-// order, in part[block].  kEmFused: first the stop rule (EmStop).
-template <int kMode>
+// order, in part[block].  kEmFused: first the stop rule (EmStop).  Each
+// wavefront takes kERows consecutive rows (a workgroup of e_threads(kERows)).
+template <int kMode, int kERows>
 __device__ __forceinline__ void estep_body(
     const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
     const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
     double2 *__restrict__ part, int nb, DevState *st, const EmStop &stp, int block) {
 #pragma clang fp contract(off)
+    constexpr int kEThreads = e_threads(kERows);
+    static_assert(kRowsPerBlock % kERows == 0 && kEChunk % kEThreads == 0,
+                  "whole rows per wavefront, whole staging rounds");
     __shared__ float4 s_xy[kEChunk];
     __shared__ float4 s_q[kEChunk];
     __shared__ float2 s_ps[kEChunk];   // (p_j, s_j - 1)
     __shared__ double2 s_part[kRowsPerBlock];
     if (kMode == kEmBatch && (st->status < 0 || st->done)) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int i = block * kRowsPerBlock + (threadIdx.x >> 6);
-    const bool active = i < n;
+    // the wavefront's rows i0, i0 + 1, ..., i0 + kERows - 1 (consecutive, so
+    // the first is active if any is)
+    const int i0 = block * kRowsPerBlock + (threadIdx.x >> 6) * kERows;
+    const bool active = i0 < n;
     // staging: a chunk's loads into registers, then LDS
-    constexpr int kPer = kEChunk / kEmThreads;
+    constexpr int kPer = kEChunk / kEThreads;
     float4 v[kPer], qv[kPer];
     float pv[kPer], sv[kPer];
     auto load_chunk = [&](int c0, int cn) {
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int t = threadIdx.x + k * kEmThreads;
+            const int t = threadIdx.x + k * kEThreads;
             if (t < cn) {
                 v[k] = xy[c0 + t];
                 qv[k] = q[c0 + t];
@@ -860,13 +877,18 @@ __device__ __forceinline__ void estep_body(
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int t = threadIdx.x + k * kEmThreads;
+            const int t = threadIdx.x + k * kEThreads;
             if (t < cn) { s_xy[t] = v[k]; s_q[t] = qv[k]; s_ps[t] = make_float2(pv[k], sv[k] - 1.f); }
         }
         __syncthreads();
     };
-    const float4 me = active ? xy[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float p_own = p[min(i, n - 1)];   // unconditional, in bounds; used if active
+    float4 me[kERows];
+    float p_own[kERows];   // unconditional, in bounds; used if the row is active
+#pragma unroll
+    for (int r = 0; r < kERows; ++r) {
+        me[r] = i0 + r < n ? xy[i0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
+        p_own[r] = p[min(i0 + r, n - 1)];
+    }
     if (kMode == kEmSingle) {
         // the first chunk's loads are issued before the stop flag's
         load_chunk(0, min(kEChunk, n));
@@ -890,7 +912,7 @@ __device__ __forceinline__ void estep_body(
             return;
         }
         if (stp.it >= 2) {   // the M-step before formed the posteriors of it - 1
-            for (int b = threadIdx.x + kEmThreads; b < nb; b += kEmThreads) any |= stp.chg[b];
+            for (int b = threadIdx.x + kEThreads; b < nb; b += kEThreads) any |= stp.chg[b];
             any = __syncthreads_or(any);
             const int rule = stop_rule(stp.it - 1, any, stp.max_iter);
             if (lead) {
@@ -910,7 +932,9 @@ __device__ __forceinline__ void estep_body(
         publish();   // nothing below changes the state
     }
     bool preloaded = kMode != kEmBatch;   // the first chunk's registers are loaded already
-    float W = 0.f, Gd = 0.f, Cd = 0.f, Sn = 0.f, X = 0.f, Y = 0.f;
+    float W[kERows], Gd[kERows], Cd[kERows], Sn[kERows], X[kERows], Y[kERows];
+#pragma unroll
+    for (int r = 0; r < kERows; ++r) W[r] = Gd[r] = Cd[r] = Sn[r] = X[r] = Y[r] = 0.f;
     for (int c0 = 0; c0 < n; c0 += kEChunk) {
         const int cn = min(kEChunk, n - c0);
         if (!preloaded) load_chunk(c0, cn);
@@ -922,14 +946,18 @@ __device__ __forceinline__ void estep_body(
         if (active) {
             auto acc1 = [&](const float4 &v, const float2 &ps, const float4 &qj) {
 #pragma clang fp contract(off)
-                const float dx = v.x - me.x, dy = v.y - me.y;
-                const float w = fast_exp2(nal2 * __builtin_fmaf(dx, dx, dy * dy)) * ps.x;
-                W += w;
-                Gd = __builtin_fmaf(w, ps.y, Gd);
-                Cd = __builtin_fmaf(w, qj.x - 1.f, Cd);
-                Sn = __builtin_fmaf(w, qj.y, Sn);
-                X = __builtin_fmaf(w, qj.z, X);
-                Y = __builtin_fmaf(w, qj.w, Y);
+                const float qc = qj.x - 1.f;
+#pragma unroll
+                for (int r = 0; r < kERows; ++r) {
+                    const float dx = v.x - me[r].x, dy = v.y - me[r].y;
+                    const float w = fast_exp2(nal2 * __builtin_fmaf(dx, dx, dy * dy)) * ps.x;
+                    W[r] += w;
+                    Gd[r] = __builtin_fmaf(w, ps.y, Gd[r]);
+                    Cd[r] = __builtin_fmaf(w, qc, Cd[r]);
+                    Sn[r] = __builtin_fmaf(w, qj.y, Sn[r]);
+                    X[r] = __builtin_fmaf(w, qj.z, X[r]);
+                    Y[r] = __builtin_fmaf(w, qj.w, Y[r]);
+                }
             };
             int t = lane;
             for (; t + 3 * kWave < cn; t += 4 * kWave) {   // 4 LDS reads in flight
@@ -947,28 +975,28 @@ __device__ __forceinline__ void estep_body(
             for (; t < cn; t += kWave) acc1(s_xy[t], s_ps[t], s_q[t]);
         }
     }
-    double2 mine = make_double2(0.0, 0.0);
-    if (active) {
-        W = wave_sum(W);
-        Gd = wave_sum(Gd);
-        Cd = wave_sum(Cd);
-        Sn = wave_sum(Sn);
-        X = wave_sum(X);
-        Y = wave_sum(Y);
-        float err = __builtin_huge_valf();
-        if (W > 0.f) {
-            // e = y_i - F(x_i) = (y_i - x_i) - D(x_i)
-            const float2 d = blend_displacement(W, Cd, Sn, X, Y, Gd, me.x, me.y);
-            const float ex = (me.z - me.x) - d.x, ey = (me.w - me.y) - d.y;
-            err = __builtin_fmaf(ex, ex, ey * ey);
+#pragma unroll
+    for (int r = 0; r < kERows; ++r) {
+        const int i = i0 + r;
+        double2 mine = make_double2(0.0, 0.0);
+        if (i < n) {
+            const float Wr = wave_sum(W[r]), Gr = wave_sum(Gd[r]), Cr = wave_sum(Cd[r]);
+            const float Sr = wave_sum(Sn[r]), Xr = wave_sum(X[r]), Yr = wave_sum(Y[r]);
+            float err = __builtin_huge_valf();
+            if (Wr > 0.f) {
+                // e = y_i - F(x_i) = (y_i - x_i) - D(x_i)
+                const float2 d = blend_displacement(Wr, Cr, Sr, Xr, Yr, Gr, me[r].x, me[r].y);
+                const float ex = (me[r].z - me[r].x) - d.x, ey = (me[r].w - me[r].y) - d.y;
+                err = __builtin_fmaf(ex, ex, ey * ey);
+            }
+            if (lane == 0) {
+                e2[i] = err;
+                const double pr = (double)p_own[r];
+                mine = make_double2(pr, pr > 0.0 ? pr * (double)err : 0.0);
+            }
         }
-        if (lane == 0) {
-            e2[i] = err;
-            const double pr = (double)p_own;
-            mine = make_double2(pr, pr > 0.0 ? pr * (double)err : 0.0);
-        }
+        if (lane == 0) s_part[(threadIdx.x / kWave) * kERows + r] = mine;
     }
-    if (lane == 0) s_part[threadIdx.x / kWave] = mine;
     __syncthreads();
     if (threadIdx.x == 0) {
         double2 r = s_part[0];
@@ -980,18 +1008,18 @@ __device__ __forceinline__ void estep_body(
     }
 }
 
-__global__ __launch_bounds__(kEmThreads) void k_estep(
+__global__ __launch_bounds__(kEThreads) void k_estep(
     const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
     const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
     double2 *__restrict__ part, DevState *st, EmStop stp) {
-    estep_body<kEmFused>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, stp, blockIdx.x);
+    estep_body<kEmFused, EMDQ_E_ROWS>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, stp, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kEmThreads) void k_estep_s(
+__global__ __launch_bounds__(kEThreads) void k_estep_s(
     const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
     const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
     double2 *__restrict__ part, DevState *st) {
-    estep_body<kEmSingle>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, EmStop{}, blockIdx.x);
+    estep_body<kEmSingle, EMDQ_E_ROWS>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, EmStop{}, blockIdx.x);
 }
 
 // Finishes an EM iteration of one pair (one workgroup of kPostThreads >=
@@ -3171,11 +3199,11 @@ __global__ __launch_bounds__(kEmThreads) void k_mstep_b(const EmJob *__restrict_
                          blockIdx.x);
 }
 
-__global__ __launch_bounds__(kEmThreads) void k_estep_b(const EmJob *__restrict__ jobs,
+__global__ __launch_bounds__(kEThreadsB) void k_estep_b(const EmJob *__restrict__ jobs,
                                                         const int *__restrict__ act) {
     const EmJob &J = jobs[act ? act[blockIdx.y] : (int)blockIdx.y];
     if ((int)blockIdx.x >= J.blocks) return;
-    estep_body<kEmBatch>(J.xy, J.p, J.q, J.s, J.n, J.nal2, J.e2, J.part, J.blocks, J.st,
+    estep_body<kEmBatch, EMDQ_E_ROWS_BATCH>(J.xy, J.p, J.q, J.s, J.n, J.nal2, J.e2, J.part, J.blocks, J.st,
                          EmStop{}, blockIdx.x);
 }
 
@@ -3664,10 +3692,10 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
                 mstep(it, 0);
             if (fused) {
                 const EmStop X{m->chg, slot, prm.max_iter, it, seq};
-                hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEmThreads), 0, stream, m->xy,
+                hipLaunchKernelGGL(k_estep, dim3(em_blocks), dim3(kEThreads), 0, stream, m->xy,
                                    m->p, m->q, m->s, n, nal2, m->e2, m->part, m->st, X);
             } else {
-                hipLaunchKernelGGL(k_estep_s, dim3(em_blocks), dim3(kEmThreads), 0, stream,
+                hipLaunchKernelGGL(k_estep_s, dim3(em_blocks), dim3(kEThreads), 0, stream,
                                    m->xy, m->p, m->q, m->s, n, nal2, m->e2, m->part, m->st);
                 hipLaunchKernelGGL(k_posterior, dim3(1), dim3(kPostThreads), 0, stream, m->p,
                                    m->e2, m->mask, n, m->part, (int)em_blocks, pp, m->st, slot,
@@ -4257,7 +4285,7 @@ emdq_status enqueue_batch_em(emdq_batch b, const EmJob *jobs, int n_pairs,
              ++c, ++enqueued) {
             mstep_b();
             hipLaunchKernelGGL(k_estep_b, dim3((unsigned)shape.max_blocks, n_act),
-                               dim3(kEmThreads), 0, stream, jobs, act);
+                               dim3(kEThreadsB), 0, stream, jobs, act);
             hipLaunchKernelGGL(k_posterior_b, dim3(n_act), dim3(kPostThreads), 0, stream, jobs,
                                act, (double)prm.sigma2_min, (double)prm.gamma_min,
                                (double)prm.gamma_max, prm.p_thresh, prm.max_iter);
