@@ -100,6 +100,9 @@ constexpr int field_waves(int rb) { return rb == 1 ? kFieldWaves : 2; }
 #ifndef EMDQ_MSTEP_ONEPASS
 #define EMDQ_MSTEP_ONEPASS 1   // M-step: centred moments from one sweep's raw moments (0: a second sweep)
 #endif
+#ifndef EMDQ_MSTEP_WSHIFT
+#define EMDQ_MSTEP_WSHIFT 1   // one-pass M-step: the weight's exponent from the moments' differences
+#endif
 #ifndef EMDQ_EM_CHUNK
 #define EMDQ_EM_CHUNK 2
 #endif
@@ -595,6 +598,14 @@ __device__ __forceinline__ void mstep_body(
     // nothing to cancellation
     const float4 sh = EMDQ_MSTEP_ONEPASS && active ? cent[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 o = make_float4(me.x + sh.x, me.y + sh.y, me.z + sh.z, me.w + sh.w);
+    // One pass: the weight's exponent from the moments' differences
+    // d = x_j - o, as nal2 |x_j - x_i|^2 = nal2 |d|^2 + 2 nal2 (o - x_i).d +
+    // nal2 |o - x_i|^2 (o - x_i as the rounded o realises it; zero at the
+    // first M-step, where this is nal2 |x_j - x_i|^2 itself).
+    constexpr bool kShiftW = EMDQ_MSTEP_ONEPASS && EMDQ_MSTEP_WSHIFT;
+    const float ox = o.x - me.x, oy = o.y - me.y;
+    const float k1x = 2.f * nal2 * ox, k1y = 2.f * nal2 * oy;
+    const float k0 = nal2 * __builtin_fmaf(ox, ox, oy * oy);
     double2 run = make_double2(0.0, 0.0);
     float e2_own = 0.f;
     uint8_t m_old = 0;
@@ -668,17 +679,22 @@ __device__ __forceinline__ void mstep_body(
         if (active) {
             auto acc1 = [&](const float4 &v, float pj, int t) {
 #pragma clang fp contract(off)
-                const float w = weight(v, pj);
-                if (kKeepW) wrow[t] = w;
                 const float dxx = v.x - o.x, dxy = v.y - o.y;   // x_j - origin
                 const float dyx = v.z - o.z, dyy = v.w - o.w;   // y_j - origin
+                const float r2 = __builtin_fmaf(dxx, dxx, dxy * dxy);
+                const float w =
+                    kShiftW ? fast_exp2(__builtin_fmaf(
+                                  nal2, r2, __builtin_fmaf(k1x, dxx, __builtin_fmaf(k1y, dxy, k0)))) *
+                                  pj
+                            : weight(v, pj);
+                if (kKeepW) wrow[t] = w;
                 S += w;
                 Ax = __builtin_fmaf(w, dxx, Ax);
                 Ay = __builtin_fmaf(w, dxy, Ay);
                 Bx = __builtin_fmaf(w, dyx, Bx);
                 By = __builtin_fmaf(w, dyy, By);
                 if constexpr (EMDQ_MSTEP_ONEPASS) {
-                    Pxx = __builtin_fmaf(w, __builtin_fmaf(dxx, dxx, dxy * dxy), Pxx);
+                    Pxx = __builtin_fmaf(w, r2, Pxx);
                     Pyy = __builtin_fmaf(w, __builtin_fmaf(dyx, dyx, dyy * dyy), Pyy);
                     Pa = __builtin_fmaf(w, __builtin_fmaf(dyx, dxx, dyy * dxy), Pa);
                     Pb = __builtin_fmaf(w, __builtin_fmaf(dyy, dxx, -(dyx * dxy)), Pb);
