@@ -57,7 +57,7 @@ TRAFFIC_BYTES = round(((57.75 + 43018.16) * 262144.0 / 131085.1 + (12609.0 + 188
 # roofline fraction is computed from.
 PROFILE = dict(file="profiles/k_field_warp_f32_1280x1024_n2000.md",
                kernels=["k_field_tables", "k_field<1, 4, 1, true>"],
-               kernel_avg_us=[8.13, 197.46], avg_launch_ms=0.20559)
+               kernel_avg_us=[7.84, 195.67], avg_launch_ms=0.20351)
 WORKLOADS = ("production", "fhd-f32", "fhd-f16", "fhd-bf16", "batch64", "batch64-learned")
 
 
