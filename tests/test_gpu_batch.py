@@ -407,3 +407,41 @@ def test_whole_step_captured_in_one_graph(learned):
                 assert torch.equal(sg[i], se[i]), (rep, i)
     print(f"whole step in one graph ({'learned' if learned else 'plain'} start): "
           f"iterations {[r['iters'] for r in want]}", flush=True)
+
+
+def test_batch_with_failed_and_capped_pairs_matches_single_calls():
+    """Pairs leave the batched EM's launches once the stop flags show them
+    fitted or failed.  A batch mixing a pair with a non-finite coordinate
+    (fails at load), pairs that stop after a few iterations and a large pair
+    that runs long: every pair's status, iterations and results equal its
+    single-pair fit bit for bit, also under an iteration cap."""
+    torch = torch_or_skip()
+    E = emdq()
+    pairs = synth.gen_batch(5, seed=3021, with_frame=False)
+    bad = synth.gen_config(1, 4, with_frame=False)
+    dst_bad = bad.dst.copy()
+    dst_bad[3, 1] = np.nan
+    srcs = [p.src for p in pairs] + [bad.src]
+    dsts = [p.dst for p in pairs] + [dst_bad]
+    sizes = [(p.cfg.width, p.cfg.height) for p in pairs] + [(bad.cfg.width, bad.cfg.height)]
+    order = [5, 0, 1, 2, 3, 4]   # the failing pair first
+    srcs = [to_dev(srcs[i], torch) for i in order]
+    dsts = [to_dev(dsts[i], torch) for i in order]
+    sizes = [sizes[i] for i in order]
+    for max_iter in (4, 9, 50):   # all capped; some capped, some converged; none capped
+        prm = E.emdq_params_default()
+        prm.max_iter = max_iter
+        mb = [E.Model(int(s.shape[0])) for s in srcs]
+        b = E.Batch(len(srcs))
+        b.fit(mb, srcs, dsts, sizes, params=prm)
+        for i, (s, d, (w, h)) in enumerate(zip(srcs, dsts, sizes)):
+            m = E.Model(int(s.shape[0]))
+            m.fit(s, d, w, h, params=prm)
+            rs, rb = m.results(), mb[i].results()
+            print(f"max_iter {max_iter} pair {i}: status {rs['status']} iters {rs['iters']}",
+                  flush=True)
+            assert rb["status"] == rs["status"] and rb["iters"] == rs["iters"], (max_iter, i)
+            if rs["status"] >= 0:
+                for key in ("p", "q", "scale", "mask"):
+                    assert np.array_equal(rb[key], rs[key]), (max_iter, i, key)
+        assert mb[0].status() == E.ENONFINITE
