@@ -30,6 +30,9 @@ Prints one JSON line.  value = frame pixels x steps / wall time of the timed
 steps (Mpix/s).  The roofline object covers the field + warp kernel, timed
 with HIP events on the stream it runs on; cpu_baseline times the FP64 oracle
 on the host cores on whole steps of the same workload (a bounded sample).
+Unless --no-extras, steady_clocks repeats the timed steps after --settle more
+untimed steps (the GPU's clocks take a few dozen steps to settle after idle);
+it is reported beside the headline, not in it.
 """
 import argparse
 import json
@@ -65,7 +68,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--settle", type=int, default=50,
+                    help="extra untimed steps before the steady-clock repeat (extras)")
     ap.add_argument("--pair", type=int, default=1)
     ap.add_argument("--workload", choices=WORKLOADS, default="production")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -385,15 +390,18 @@ def main():
         if r["status"] < 0:
             raise SystemExit(f"fit failed: {E.status_string(r['status'])}")
 
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        R.step(stream, events[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    warp_times = np.array([a.elapsed_time(b) for a, b in events])
+    def timed(steps):
+        """Wall time of `steps` steps and the HIP-event time of each warp call."""
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            R.step(stream, evs[k])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, np.array([a.elapsed_time(b) for a, b in evs])
+
+    wall, warp_times = timed(args.steps)
     warp_ms = float(np.mean(warp_times))
 
     pix = sum(w * h for w, h in sizes)
@@ -444,6 +452,19 @@ def main():
                vs_baseline=None, dtype=prec, data="synthetic",
                config=cfg, warp_only_mpix_s=round(pix / (warp_ms * 1e-3) / 1e6, 2),
                fit_ms=round(ms_per_step - warp_ms, 4), roofline=roofline, learned_init=None)
+    if not args.no_extras:
+        # The same timed steps again once the GPU's clocks have settled: the
+        # first few dozen steps after idle run at lower clocks.  Outside the
+        # headline (which is the steps above).
+        for _ in range(args.settle):
+            R.step(stream)
+        w2, t2 = timed(args.steps)
+        m2 = float(np.mean(t2))
+        out["steady_clocks"] = dict(
+            untimed_steps_before=args.warmup + args.steps + args.settle, steps=args.steps,
+            ms_per_step=round(w2 / args.steps * 1e3, 4),
+            value=round(pix * args.steps / w2 / 1e6, 3), warp_ms=round(m2, 5),
+            frac=round(flops / (m2 * 1e-3) / 1e12 / peak, 4))
     if wl == "production" and not args.no_extras:
         out["learned_init"] = learned_vs_plain(E, torch, pairs[0], stream)
         out["learned_init_fhd_n5000"] = learned_vs_plain(E, torch, synth.gen_config(5, 1),
