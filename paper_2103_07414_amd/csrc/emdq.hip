@@ -43,7 +43,7 @@ namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kWave = 64;
-constexpr int kRowsPerBlock = 8;        // EM kernels: one wavefront per match
+constexpr int kRowsPerBlock = 8;        // EM kernels: match rows per workgroup
 template <int V> struct IntTag { static constexpr int value = V; };
 constexpr int kEmThreads = kWave * kRowsPerBlock;
 // E-step: match rows per wavefront (each staged match is read from LDS once
