@@ -63,8 +63,12 @@ constexpr int kEThreadsB = e_threads(EMDQ_E_ROWS_BATCH);  // batched E-step work
 #ifndef EMDQ_ECHUNK
 #define EMDQ_ECHUNK 1024
 #endif
+#ifndef EMDQ_ECHUNK_BATCH
+#define EMDQ_ECHUNK_BATCH 512
+#endif
 constexpr int kMChunk = EMDQ_MCHUNK;    // matches staged in LDS per M-step sweep
-constexpr int kEChunk = EMDQ_ECHUNK;    // matches (+ fits) staged per E-step sweep
+constexpr int kEChunk = EMDQ_ECHUNK;    // matches (+ fits) staged per E-step sweep, single pair
+constexpr int kEChunkB = EMDQ_ECHUNK_BATCH;   // the same, batched E-step (more workgroups per CU)
 constexpr int kCompactThreads = 1024;
 constexpr int kFieldThreads = 256;      // 4 wavefronts per workgroup
 constexpr int kTile = 32;               // 32 x 32 pixels per MFMA output tile
@@ -848,19 +852,20 @@ struct EmStop {
 // normalisation, prediction y_hat = s (R x_i + t) (Eq. (1)), residual e_i^2.
 // The workgroup also leaves (sum p_i, sum p_i e_i^2) over its rows, in row
 // order, in part[block].  kEmFused: first the stop rule (EmStop).  Each
-// wavefront takes kERows consecutive rows (a workgroup of e_threads(kERows)).
-template <int kMode, int kERows>
+// wavefront takes kERows consecutive rows (a workgroup of e_threads(kERows));
+// kChunk matches (and fits) are staged in LDS per sweep.
+template <int kMode, int kERows, int kChunk>
 __device__ __forceinline__ void estep_body(
     const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
     const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
     double2 *__restrict__ part, int nb, DevState *st, const EmStop &stp, int block) {
 #pragma clang fp contract(off)
     constexpr int kEThreads = e_threads(kERows);
-    static_assert(kRowsPerBlock % kERows == 0 && kEChunk % kEThreads == 0,
+    static_assert(kRowsPerBlock % kERows == 0 && kChunk % kEThreads == 0,
                   "whole rows per wavefront, whole staging rounds");
-    __shared__ float4 s_xy[kEChunk];
-    __shared__ float4 s_q[kEChunk];
-    __shared__ float2 s_ps[kEChunk];   // (p_j, s_j - 1)
+    __shared__ float4 s_xy[kChunk];
+    __shared__ float4 s_q[kChunk];
+    __shared__ float2 s_ps[kChunk];   // (p_j, s_j - 1)
     __shared__ double2 s_part[kRowsPerBlock];
     if (kMode == kEmBatch && (st->status < 0 || st->done)) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -869,7 +874,7 @@ __device__ __forceinline__ void estep_body(
     const int i0 = block * kRowsPerBlock + (threadIdx.x >> 6) * kERows;
     const bool active = i0 < n;
     // staging: a chunk's loads into registers, then LDS
-    constexpr int kPer = kEChunk / kEThreads;
+    constexpr int kPer = kChunk / kEThreads;
     float4 v[kPer], qv[kPer];
     float pv[kPer], sv[kPer];
     auto load_chunk = [&](int c0, int cn) {
@@ -907,7 +912,7 @@ __device__ __forceinline__ void estep_body(
     }
     if (kMode == kEmSingle) {
         // the first chunk's loads are issued before the stop flag's
-        load_chunk(0, min(kEChunk, n));
+        load_chunk(0, min(kChunk, n));
         const int status = st->status, done = st->done;
         if (status < 0 || done) return;
     } else if (kMode == kEmFused) {
@@ -916,7 +921,7 @@ __device__ __forceinline__ void estep_body(
         // chg[min(t, nb - 1)] is one of the flags, so OR-ing it is harmless;
         // loaded unconditionally (unused when it = 1), the stop flag last
         const int chg0 = stp.chg[min((int)threadIdx.x, nb - 1)];
-        load_chunk(0, min(kEChunk, n));
+        load_chunk(0, min(kChunk, n));
         const int stop = __atomic_load_n(&st->stop_at, __ATOMIC_RELAXED);
         int any = stp.it >= 2 ? chg0 : 0;
         const bool lead = block == 0 && threadIdx.x == 0;
@@ -951,13 +956,13 @@ __device__ __forceinline__ void estep_body(
     float W[kERows], Gd[kERows], Cd[kERows], Sn[kERows], X[kERows], Y[kERows];
 #pragma unroll
     for (int r = 0; r < kERows; ++r) W[r] = Gd[r] = Cd[r] = Sn[r] = X[r] = Y[r] = 0.f;
-    for (int c0 = 0; c0 < n; c0 += kEChunk) {
-        const int cn = min(kEChunk, n - c0);
+    for (int c0 = 0; c0 < n; c0 += kChunk) {
+        const int cn = min(kChunk, n - c0);
         if (!preloaded) load_chunk(c0, cn);
         store_chunk(cn);
         // the next chunk's loads go out now (its registers are free once
         // this chunk is in LDS) and land during this chunk's sweep
-        if (c0 + kEChunk < n) load_chunk(c0 + kEChunk, min(kEChunk, n - c0 - kEChunk));
+        if (c0 + kChunk < n) load_chunk(c0 + kChunk, min(kChunk, n - c0 - kChunk));
         preloaded = true;
         if (active) {
             auto acc1 = [&](const float4 &v, const float2 &ps, const float4 &qj) {
@@ -1028,14 +1033,14 @@ __global__ __launch_bounds__(kEThreads) void k_estep(
     const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
     const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
     double2 *__restrict__ part, DevState *st, EmStop stp) {
-    estep_body<kEmFused, EMDQ_E_ROWS>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, stp, blockIdx.x);
+    estep_body<kEmFused, EMDQ_E_ROWS, kEChunk>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, stp, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kEThreads) void k_estep_s(
     const float4 *__restrict__ xy, const float *__restrict__ p, const float4 *__restrict__ q,
     const float *__restrict__ s, int n, float nal2, float *__restrict__ e2,
     double2 *__restrict__ part, DevState *st) {
-    estep_body<kEmSingle, EMDQ_E_ROWS>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, EmStop{}, blockIdx.x);
+    estep_body<kEmSingle, EMDQ_E_ROWS, kEChunk>(xy, p, q, s, n, nal2, e2, part, gridDim.x, st, EmStop{}, blockIdx.x);
 }
 
 // Finishes an EM iteration of one pair (one workgroup of kPostThreads >=
@@ -3219,7 +3224,7 @@ __global__ __launch_bounds__(kEThreadsB) void k_estep_b(const EmJob *__restrict_
                                                         const int *__restrict__ act) {
     const EmJob &J = jobs[act ? act[blockIdx.y] : (int)blockIdx.y];
     if ((int)blockIdx.x >= J.blocks) return;
-    estep_body<kEmBatch, EMDQ_E_ROWS_BATCH>(J.xy, J.p, J.q, J.s, J.n, J.nal2, J.e2, J.part, J.blocks, J.st,
+    estep_body<kEmBatch, EMDQ_E_ROWS_BATCH, kEChunkB>(J.xy, J.p, J.q, J.s, J.n, J.nal2, J.e2, J.part, J.blocks, J.st,
                          EmStop{}, blockIdx.x);
 }
 
