@@ -114,6 +114,19 @@ constexpr int kEmChunk = EMDQ_EM_CHUNK; // EM iterations enqueued between stop-f
 #ifndef EMDQ_START_WGS
 #define EMDQ_START_WGS 2048   // batched learned start: workgroups over all pairs
 #endif
+// learned start: one match per lane (1) or per wavefront (0) in the grid search
+#ifndef EMDQ_START_LANE
+#define EMDQ_START_LANE 1
+#endif
+// one match per lane: about this many workgroups for the features of one
+// pair (WGS1; the single-pair start keeps one match per wavefront, which
+// spreads one pair over more CUs) and for a batch (WGSB)
+#ifndef EMDQ_START_LANE_WGS1
+#define EMDQ_START_LANE_WGS1 32
+#endif
+#ifndef EMDQ_START_LANE_WGSB
+#define EMDQ_START_LANE_WGSB 512
+#endif
 #ifndef EMDQ_FUSED_MAX_N
 #define EMDQ_FUSED_MAX_N 2048
 #endif
@@ -2532,6 +2545,66 @@ __device__ __forceinline__ int grid_cell(float v, float v0, float sv, int nv) {
 }
 
 
+// The network on the block of kMlpRows matches whose features are in L.f
+// (see StartLds): wavefront w < 4 computes output block w of each layer;
+// row r's output goes to p_out[match_of(r)] when that is below n.  Three
+// barriers; the block's features may be overwritten after the second.
+template <class MatchOf>
+__device__ __forceinline__ void start_mlp(StartLds &L, int wave, int lane, float b3,
+                                          float *__restrict__ p_out, int n,
+                                          const MatchOf &match_of) {
+    const int col = lane & 31, half = lane >> 5;
+    if (wave < 4) {
+        const int ob = wave;
+        f32x16 acc;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+#pragma unroll
+        for (int ks = 0; ks < kNFeat / 16; ++ks) {
+            const bhalf8 wa = *(const bhalf8 *)&L.w1[32 * ob + col][16 * ks + 8 * half];
+            const bhalf8 fb = *(const bhalf8 *)&L.f[col][16 * ks + 8 * half];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, fb, acc, 0, 0, 0);
+        }
+        // H1[match][output] = bf16(gelu(layer 1 + b1))
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int o = 32 * ob + 8 * (q >> 2) + 4 * half + (q & 3);
+            L.h1[col][o] = (__bf16)gelu_fast(acc[q] + L.b1[o]);
+        }
+    }
+    __syncthreads();
+    if (wave < 4) {
+        const int ob2 = wave;
+        f32x16 acc;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < kNHid / 16; ++kk) {
+            const bhalf8 wa = *(const bhalf8 *)&L.w2[32 * ob2 + col][16 * kk + 8 * half];
+            const bhalf8 hb = *(const bhalf8 *)&L.h1[col][16 * kk + 8 * half];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, hb, acc, 0, 0, 0);
+        }
+        // this output block's share of the logit of match col: the lane's 16
+        // rows, then the two halves (same order in both)
+        float zp = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int o = 32 * ob2 + 8 * (q >> 2) + 4 * half + (q & 3);
+            zp += L.w3[o] * gelu_fast(acc[q] + L.b2[o]);
+        }
+        const float zo = __shfl_xor(zp, 32, kWave);
+        if (half == 0) L.zpart[ob2][col] = zp + zo;
+    }
+    __syncthreads();
+    if (wave == 0 && lane < kMlpRows) {
+        // the four output blocks' shares added in block order
+        const float z = ((L.zpart[0][lane] + L.zpart[1][lane]) + L.zpart[2][lane]) +
+                        L.zpart[3][lane] + b3;
+        const int im = match_of(lane);
+        if (im < n) p_out[im] = 1.f / (1.f + expf(-z));
+    }
+}
+
 // With feat_out set, the features are written out ([n][64]) and the network
 // is not evaluated (wts and p_out unused).
 __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
@@ -2539,9 +2612,17 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
                                            const float *__restrict__ wts,
                                            float *__restrict__ p_out,
                                            float *__restrict__ feat_out, int block,
-                                           int nblocks) {
+                                           int nblocks, int lanes) {
     __shared__ StartLds L;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    // lanes > 0: the grid search takes one match per lane, lanes matches per
+    // wavefront, kStartWaves * lanes per workgroup and round; the workgroups
+    // past the pair's matches have nothing to do (and every path below
+    // strides over the others only)
+    if (lanes > 0) {
+        nblocks = min(nblocks, (n + kStartWaves * lanes - 1) / (kStartWaves * lanes));
+        if (block >= nblocks) return;
+    }
     float b3 = 0.f;
     if (!feat_out) {
         const float *W1 = wts, *B1 = W1 + kNHid * kNFeat, *W2 = B1 + kNHid;
@@ -2706,6 +2787,140 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
         }
         __syncthreads();
         // gs[c] now holds the end of cell c, i.e. the start of cell c + 1
+        if (lanes > 0) {
+            // each cell's points by match index, so that a position in the
+            // grid names the same match in every workgroup of the pair (the
+            // one-match-per-lane rounds go by position)
+            for (int c = tid; c < gnx * gny; c += kStartThreads) {
+                const int a = c == 0 ? 0 : L.gs[c - 1], e = L.gs[c];
+                for (int u = a + 1; u < e; ++u) {   // insertion sort, a few points
+                    const uint16_t key = L.gi[u];
+                    const float2 pt = L.gp[u];
+                    int v = u - 1;
+                    for (; v >= a && L.gi[v] > key; --v) {
+                        L.gi[v + 1] = L.gi[v];
+                        L.gp[v + 1] = L.gp[v];
+                    }
+                    L.gi[v + 1] = key;
+                    L.gp[v + 1] = pt;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    if (lanes > 0 && grid) {
+        // ---- one match per lane: each lane searches the rings of cells
+        // around its match on its own (the same rings and stopping rule as
+        // below), keeping its sorted list of the 16 nearest by (squared
+        // distance, index) -- the neighbours themselves, in order.  The
+        // matches are taken in the grid's cell order (every point is finite
+        // here), so the lanes of a wavefront search neighbouring cells.
+        const float gx0 = L.gbox[0][0], gy0 = L.gbox[0][1];
+        const float gsx = L.gbox[0][2], gsy = L.gbox[0][3];
+        const int gnx = L.gdim[0], gny = L.gdim[1];
+        const double margin = (double)L.gmargin;
+        const int per_round = kStartWaves * lanes;
+        const int li = wave * lanes + lane;   // the lane's place in a round
+        for (int base = block * per_round; base < n; base += nblocks * per_round) {
+            const int pos = base + li;
+            const bool act = lane < lanes && pos < n;
+            const int i = act ? (int)L.gi[pos] : 0;
+            double bd[kKnn];
+            int bj[kKnn];
+#pragma unroll
+            for (int k = 0; k < kKnn; ++k) { bd[k] = __builtin_huge_val(); bj[k] = 0x7fffffff; }
+            auto insert = [&](double d2, int j) {
+                if (!key_less(d2, j, bd[kKnn - 1], bj[kKnn - 1])) return;
+#pragma unroll
+                for (int k = kKnn - 1; k >= 1; --k) {
+                    const bool shift = key_less(d2, j, bd[k - 1], bj[k - 1]);
+                    const bool here = !shift && key_less(d2, j, bd[k], bj[k]);
+                    bd[k] = shift ? bd[k - 1] : (here ? d2 : bd[k]);
+                    bj[k] = shift ? bj[k - 1] : (here ? j : bj[k]);
+                }
+                if (key_less(d2, j, bd[0], bj[0])) { bd[0] = d2; bj[0] = j; }
+            };
+            const float2 xi = act ? L.gp[pos] : make_float2(0.f, 0.f);
+            if (act) {
+                const int cx = grid_cell(xi.x, gx0, gsx, gnx), cy = grid_cell(xi.y, gy0, gsy, gny);
+                auto cell_start = [&](int c) { return c == 0 ? 0 : L.gs[c - 1]; };
+                auto row = [&](int y, int xa, int xb) {   // cells xa..xb of row y
+                    const int e = L.gs[y * gnx + xb];
+                    for (int q = cell_start(y * gnx + xa); q < e; ++q) {
+                        const int j = L.gi[q];
+                        if (j != i) insert(dist2_f64(xi, L.gp[q]), j);
+                    }
+                };
+                for (int R = 0;; ++R) {
+                    const int xa = max(cx - R, 0), xb = min(cx + R, gnx - 1);
+                    const int ya = max(cy - R, 0), yb = min(cy + R, gny - 1);
+                    if (R == 0) {
+                        row(cy, cx, cx);
+                    } else {
+                        if (cy - R >= 0) row(cy - R, xa, xb);
+                        if (cy + R < gny) row(cy + R, xa, xb);
+                        for (int y = max(cy - R + 1, 0); y <= min(cy + R - 1, gny - 1); ++y) {
+                            if (cx - R >= 0) row(y, cx - R, cx - R);
+                            if (cx + R < gnx) row(y, cx + R, cx + R);
+                        }
+                    }
+                    if (xa == 0 && xb == gnx - 1 && ya == 0 && yb == gny - 1) break;
+                    double bound = __builtin_huge_val();
+                    if (xa > 0) bound = fmin(bound, (double)xi.x - ((double)gx0 + (double)xa * gsx));
+                    if (xb < gnx - 1)
+                        bound = fmin(bound, ((double)gx0 + (double)(xb + 1) * gsx) - (double)xi.x);
+                    if (ya > 0) bound = fmin(bound, (double)xi.y - ((double)gy0 + (double)ya * gsy));
+                    if (yb < gny - 1)
+                        bound = fmin(bound, ((double)gy0 + (double)(yb + 1) * gsy) - (double)xi.y);
+                    bound -= margin;
+                    // 16 kept candidates closer than any unsearched point
+                    if (bound > 0.0 && bd[kKnn - 1] < bound * bound) break;
+                }
+            }
+            // ---- features of neighbour k (zero where fewer than 16 exist)
+            float4 fv[kKnn];
+            const float2 yi = act ? dst[i] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int k = 0; k < kKnn; ++k) {
+                fv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (act && bj[k] != 0x7fffffff) {
+                    const float2 xj = src[bj[k]], yj = dst[bj[k]];
+                    float ex = ((yj.x - xj.x) - (yi.x - xi.x)) * 0.125f;
+                    float ey = ((yj.y - xj.y) - (yi.y - xi.y)) * 0.125f;
+                    fv[k] = make_float4(g * (xj.x - xi.x), g * (xj.y - xi.y),
+                                        ex / (1.f + fabsf(ex)), ey / (1.f + fabsf(ey)));
+                }
+            }
+            if (feat_out) {
+                if (act)
+#pragma unroll
+                    for (int k = 0; k < kKnn; ++k)
+                        *(float4 *)&feat_out[(size_t)i * kNFeat + 4 * k] = fv[k];
+                continue;
+            }
+            // ---- the network on blocks of kMlpRows consecutive places
+            for (int b0 = 0; b0 < per_round && base + b0 < n; b0 += kMlpRows) {   // uniform
+                if (lane < lanes && li >= b0 && li < b0 + kMlpRows) {   // its own row
+#pragma unroll
+                    for (int k = 0; k < kKnn; ++k) {
+                        bhalf4 fb;
+                        fb[0] = (__bf16)fv[k].x;
+                        fb[1] = (__bf16)fv[k].y;
+                        fb[2] = (__bf16)fv[k].z;
+                        fb[3] = (__bf16)fv[k].w;
+                        *(bhalf4 *)&L.f[li - b0][4 * k] = fb;
+                    }
+                }
+                __syncthreads();   // the block's features are complete
+                const int lim = min(n, base + per_round);
+                start_mlp(L, wave, lane, b3, p_out, n, [&](int r) {
+                    const int q = base + b0 + r;
+                    return q < lim ? (int)L.gi[q] : n;
+                });
+            }
+        }
+        return;
     }
 
     // The workgroup's matches in rounds t = 0, 1, ...: in round t wavefront w
@@ -2884,58 +3099,9 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
     }
     if (feat_out) continue;
     __syncthreads();   // the block's features are complete
-    // ---- network on the block (see StartLds): wavefront w < 4 computes
-    // output block w of each layer
-    const int col = lane & 31, half = lane >> 5;
-    if (wave < 4) {
-        const int ob = wave;
-        f32x16 acc;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.f;
-#pragma unroll
-        for (int ks = 0; ks < kNFeat / 16; ++ks) {
-            const bhalf8 wa = *(const bhalf8 *)&L.w1[32 * ob + col][16 * ks + 8 * half];
-            const bhalf8 fb = *(const bhalf8 *)&L.f[col][16 * ks + 8 * half];
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, fb, acc, 0, 0, 0);
-        }
-        // H1[match][output] = bf16(gelu(layer 1 + b1))
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int o = 32 * ob + 8 * (q >> 2) + 4 * half + (q & 3);
-            L.h1[col][o] = (__bf16)gelu_fast(acc[q] + L.b1[o]);
-        }
-    }
-    __syncthreads();
-    if (wave < 4) {
-        const int ob2 = wave;
-        f32x16 acc;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < kNHid / 16; ++kk) {
-            const bhalf8 wa = *(const bhalf8 *)&L.w2[32 * ob2 + col][16 * kk + 8 * half];
-            const bhalf8 hb = *(const bhalf8 *)&L.h1[col][16 * kk + 8 * half];
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, hb, acc, 0, 0, 0);
-        }
-        // this output block's share of the logit of match col: the lane's 16
-        // rows, then the two halves (same order in both)
-        float zp = 0.f;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int o = 32 * ob2 + 8 * (q >> 2) + 4 * half + (q & 3);
-            zp += L.w3[o] * gelu_fast(acc[q] + L.b2[o]);
-        }
-        const float zo = __shfl_xor(zp, 32, kWave);
-        if (half == 0) L.zpart[ob2][col] = zp + zo;
-    }
-    __syncthreads();
-    if (wave == 0 && lane < kMlpRows) {
-        // the four output blocks' shares added in block order
-        const float z = ((L.zpart[0][lane] + L.zpart[1][lane]) + L.zpart[2][lane]) +
-                        L.zpart[3][lane] + b3;
-        const int im = g0 + (lane / kStartWaves) * stride + lane % kStartWaves;
-        if (im < n) p_out[im] = 1.f / (1.f + expf(-z));
-    }
+    start_mlp(L, wave, lane, b3, p_out, n, [&](int r) {
+        return g0 + (r / kStartWaves) * stride + r % kStartWaves;
+    });
     // the next group's features overwrite the block only after the barrier
     // at its end, so these reads of zpart are done before zpart is written
     // again
@@ -2944,14 +3110,22 @@ __device__ __forceinline__ void start_body(const float2 *__restrict__ src,
 
 __global__ __launch_bounds__(kStartThreads) void k_start(
     const float2 *__restrict__ src, const float2 *__restrict__ dst, int n, float g,
-    const float *__restrict__ wts, float *__restrict__ p_out) {
-    start_body(src, dst, n, g, wts, p_out, nullptr, blockIdx.x, gridDim.x);
+    const float *__restrict__ wts, float *__restrict__ p_out, int lanes) {
+    start_body(src, dst, n, g, wts, p_out, nullptr, blockIdx.x, gridDim.x, lanes);
 }
 
 __global__ __launch_bounds__(kStartThreads) void k_start_features(
     const float2 *__restrict__ src, const float2 *__restrict__ dst, int n, float g,
-    float *__restrict__ feat_out) {
-    start_body(src, dst, n, g, nullptr, nullptr, feat_out, blockIdx.x, gridDim.x);
+    float *__restrict__ feat_out, int lanes) {
+    start_body(src, dst, n, g, nullptr, nullptr, feat_out, blockIdx.x, gridDim.x, lanes);
+}
+
+// Matches per wavefront of the one-match-per-lane search (0: one match per
+// wavefront) for `matches` matches spread over about `wgs` workgroups.
+int start_lanes(long long matches, int wgs) {
+    if (!EMDQ_START_LANE) return 0;
+    const long long l = (matches + (long long)kStartWaves * wgs - 1) / ((long long)kStartWaves * wgs);
+    return (int)std::min<long long>(std::max<long long>(l, 8), kWave);
 }
 
 struct StartJob {
@@ -2964,9 +3138,10 @@ struct StartJob {
 // One launch for many pairs: blockIdx.y = pair, the pair's matches strided
 // over the gridDim.x workgroups.
 __global__ __launch_bounds__(kStartThreads) void k_start_b(const StartJob *__restrict__ jobs,
-                                                           const float *__restrict__ wts) {
+                                                           const float *__restrict__ wts,
+                                                           int lanes) {
     const StartJob &J = jobs[blockIdx.y];
-    start_body(J.src, J.dst, J.n, J.g, wts, J.p_out, nullptr, blockIdx.x, gridDim.x);
+    start_body(J.src, J.dst, J.n, J.g, wts, J.p_out, nullptr, blockIdx.x, gridDim.x, lanes);
 }
 
 // EM start from given posteriors: xy as k_load, p = init_p, mask = p > thresh
@@ -3866,7 +4041,7 @@ emdq_status emdq_learned_start(const float *src_xy, const float *dst_xy, int n, 
     int blocks = (n + kStartWaves - 1) / kStartWaves;
     if (blocks > 1024) blocks = 1024;   // each workgroup stages the weights once
     hipLaunchKernelGGL(k_start, dim3((unsigned)blocks), dim3(kStartThreads), 0, stream,
-                       (const float2 *)src_xy, (const float2 *)dst_xy, n, g, weights, p_out);
+                       (const float2 *)src_xy, (const float2 *)dst_xy, n, g, weights, p_out, 0);
     return check_launch();
 }
 
@@ -3881,8 +4056,10 @@ emdq_status emdq_start_features(const float *src_xy, const float *dst_xy, int n,
     const float g = (float)sqrt(alpha_d(prm, frame_w, frame_h));
     int blocks = (n + kStartWaves - 1) / kStartWaves;
     if (blocks > 4096) blocks = 4096;
+    const int lanes = start_lanes(n, EMDQ_START_LANE_WGS1);
+    if (lanes > 0) blocks = (n + kStartWaves * lanes - 1) / (kStartWaves * lanes);
     hipLaunchKernelGGL(k_start_features, dim3((unsigned)blocks), dim3(kStartThreads), 0, stream,
-                       (const float2 *)src_xy, (const float2 *)dst_xy, n, g, feat_out);
+                       (const float2 *)src_xy, (const float2 *)dst_xy, n, g, feat_out, lanes);
     return check_launch();
 }
 
@@ -4001,7 +4178,8 @@ struct emdq_batch_s {
     StartJob *step_start = nullptr;
     FieldJob *step_field = nullptr;
     bool step_ready = false;
-    int step_pairs = 0, step_start_wgs = 0, step_variant = 0, step_tab_rows = 0;
+    int step_pairs = 0, step_start_wgs = 0, step_start_lanes = 0, step_variant = 0,
+        step_tab_rows = 0;
     int step_shape_blocks = 1, step_shape_n = 2;
     long long step_blocks = 0;
     const float *step_weights = nullptr;
@@ -4352,7 +4530,7 @@ emdq_status enqueue_batch_em(emdq_batch b, const EmJob *jobs, int n_pairs,
 emdq_status fill_start_jobs(emdq_batch b, StartJob *jobs, int n_pairs,
                             const float *const *src_xy, const float *const *dst_xy, const int *n,
                             const int *frame_w, const int *frame_h, const emdq_params *params,
-                            float *const *p_out, int *per) {
+                            float *const *p_out, int *per, int *lanes) {
     if (!b || !src_xy || !dst_xy || !n || !frame_w || !frame_h || !p_out) return EMDQ_EINVAL;
     if (n_pairs < 1 || n_pairs > b->max_pairs) return EMDQ_EINVAL;
     emdq_params prm;
@@ -4371,11 +4549,15 @@ emdq_status fill_start_jobs(emdq_batch b, StartJob *jobs, int n_pairs,
         if (n[i] > max_n) max_n = n[i];
     }
     // enough workgroups per pair to cover the largest one; about
-    // EMDQ_START_WGS in all
+    // EMDQ_START_WGS in all (one match per wavefront), or about 512 with
+    // one match per lane
     int wgs = (EMDQ_START_WGS + n_pairs - 1) / n_pairs;
     const int need = (max_n + kStartWaves - 1) / kStartWaves;
     if (wgs > need) wgs = need;
+    const int l = start_lanes((long long)max_n * n_pairs, EMDQ_START_LANE_WGSB);
+    if (l > 0) wgs = (max_n + kStartWaves * l - 1) / (kStartWaves * l);
     *per = wgs;
+    *lanes = l;
     return EMDQ_OK;
 }
 
@@ -4472,15 +4654,15 @@ emdq_status emdq_batch_learned_start(emdq_batch b, int n_pairs, const float *con
     int slot = 0;
     StartJob *jobs = (StartJob *)batch_slot(b, &slot);
     if (!jobs) return EMDQ_EHIP;
-    int per = 0;
+    int per = 0, lanes = 0;
     const emdq_status rc = fill_start_jobs(b, jobs, n_pairs, src_xy, dst_xy, n, frame_w,
-                                           frame_h, params, p_out, &per);
+                                           frame_h, params, p_out, &per, &lanes);
     if (rc != EMDQ_OK) return rc;
     EMDQ_HIP(hipMemcpyAsync(b->start_jobs, jobs, sizeof(StartJob) * n_pairs,
                             hipMemcpyHostToDevice, stream));
     EMDQ_HIP(hipEventRecord(b->stage_done[slot], stream));
     hipLaunchKernelGGL(k_start_b, dim3((unsigned)per, (unsigned)n_pairs), dim3(kStartThreads), 0,
-                       stream, b->start_jobs, weights);
+                       stream, b->start_jobs, weights, lanes);
     return check_launch();
 }
 
@@ -4599,13 +4781,13 @@ emdq_status emdq_batch_prepare_step(emdq_batch b, int n_pairs, const emdq_model 
     StartJob *st = (StartJob *)(host + sizeof(EmJob) * (size_t)n_pairs);
     FieldJob *fj = (FieldJob *)(host + (sizeof(EmJob) + sizeof(StartJob)) * (size_t)n_pairs);
     BatchEmShape shape;
-    int wgs = 0, v = 0, tab_rows = 0;
+    int wgs = 0, lanes = 0, v = 0, tab_rows = 0;
     long long blocks = 0;
     rc = fill_em_jobs(b, em, n_pairs, models, src_xy, dst_xy, n, frame_w, frame_h,
                       start_weights ? (const float *const *)start_p : nullptr, params, &shape);
     if (rc == EMDQ_OK && start_weights)
         rc = fill_start_jobs(b, st, n_pairs, src_xy, dst_xy, n, frame_w, frame_h, params,
-                             start_p, &wgs);
+                             start_p, &wgs, &lanes);
     if (rc == EMDQ_OK) {
         v = batch_variant(b, n_pairs, regions);
         rc = fill_field_jobs(fj, n_pairs, models, regions, kVariantSplitK[v], kVariantRows[v],
@@ -4624,6 +4806,7 @@ emdq_status emdq_batch_prepare_step(emdq_batch b, int n_pairs, const emdq_model 
     if (params) b->step_prm = *params; else emdq_params_default(&b->step_prm);
     b->step_pairs = n_pairs;
     b->step_start_wgs = wgs;
+    b->step_start_lanes = lanes;
     b->step_weights = start_weights;
     b->step_variant = v;
     b->step_blocks = blocks;
@@ -4639,7 +4822,7 @@ emdq_status emdq_batch_launch_step(emdq_batch b, hipStream_t stream) {
     const unsigned P = (unsigned)b->step_pairs;
     if (b->step_weights)
         hipLaunchKernelGGL(k_start_b, dim3((unsigned)b->step_start_wgs, P), dim3(kStartThreads),
-                           0, stream, b->step_start, b->step_weights);
+                           0, stream, b->step_start, b->step_weights, b->step_start_lanes);
     BatchEmShape shape;
     shape.max_blocks = b->step_shape_blocks;
     shape.max_n = b->step_shape_n;
