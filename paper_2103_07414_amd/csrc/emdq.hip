@@ -66,9 +66,16 @@ constexpr int kEThreadsB = e_threads(EMDQ_E_ROWS_BATCH);  // batched E-step work
 #ifndef EMDQ_ECHUNK_BATCH
 #define EMDQ_ECHUNK_BATCH 512
 #endif
+#ifndef EMDQ_MCHUNK_BATCH
+#define EMDQ_MCHUNK_BATCH 2048
+#endif
+#ifndef EMDQ_MSTEP_B_WAVES
+#define EMDQ_MSTEP_B_WAVES 0   // batched M-step: wavefronts per SIMD the registers are held to (0: free)
+#endif
 constexpr int kMChunk = EMDQ_MCHUNK;    // matches staged in LDS per M-step sweep
 constexpr int kEChunk = EMDQ_ECHUNK;    // matches (+ fits) staged per E-step sweep, single pair
 constexpr int kEChunkB = EMDQ_ECHUNK_BATCH;   // the same, batched E-step (more workgroups per CU)
+constexpr int kMChunkB = EMDQ_MCHUNK_BATCH;   // matches staged per batched M-step sweep
 constexpr int kCompactThreads = 1024;
 constexpr int kFieldThreads = 256;      // 4 wavefronts per workgroup
 constexpr int kTile = 32;               // 32 x 32 pixels per MFMA output tile
@@ -547,7 +554,7 @@ struct EmFused {
 // FP64.  (EMDQ_MSTEP_ONEPASS 0: a second sweep forms the centred moments.)
 // Then the closed-form 2D Procrustes fit.  kEmFused: the posterior step first
 // (EmFused); otherwise the posteriors are read from p.
-template <int kMode>
+template <int kMode, int kMChunk = ::kMChunk>
 __device__ __forceinline__ void mstep_body(
     const float4 *__restrict__ xy, const float *p, int n, float nal2,
     double alpha, float4 *__restrict__ q_out, float *__restrict__ s_out,
@@ -3387,11 +3394,15 @@ __global__ void k_load_b(const EmJob *__restrict__ jobs, float p_thresh) {
 // The per-iteration batch kernels take blockIdx.y (x for the posterior step)
 // as an index into act, the pairs still running, or as the pair when act is
 // null.
-__global__ __launch_bounds__(kEmThreads) void k_mstep_b(const EmJob *__restrict__ jobs,
+__global__ __launch_bounds__(kEmThreads)
+#if EMDQ_MSTEP_B_WAVES
+__attribute__((amdgpu_waves_per_eu(EMDQ_MSTEP_B_WAVES, EMDQ_MSTEP_B_WAVES)))
+#endif
+void k_mstep_b(const EmJob *__restrict__ jobs,
                                                         const int *__restrict__ act) {
     const EmJob &J = jobs[act ? act[blockIdx.y] : (int)blockIdx.y];
     if ((int)blockIdx.x >= J.blocks) return;
-    mstep_body<kEmBatch>(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.cent, J.st, 1, EmFused{},
+    mstep_body<kEmBatch, kMChunkB>(J.xy, J.p, J.n, J.nal2, J.alpha, J.q, J.s, J.cent, J.st, 1, EmFused{},
                          blockIdx.x);
 }
 
