@@ -312,6 +312,12 @@ def _batch64_against_oracle(torch, learned):
                   for p in pairs]
         b.learned_start(srcs, dsts, sizes, w, starts)
         wo = np.load(E.START_WEIGHTS, allow_pickle=False).astype(np.float64)
+        # the batch searches one match per lane, a single pair one match per
+        # wavefront: the same starts bit for bit
+        for i in range(0, len(pairs), 8):
+            o = torch.empty(pairs[i].cfg.n_matches, dtype=torch.float32, device="cuda")
+            E.emdq_learned_start(srcs[i], dsts[i], *sizes[i], w, o)
+            assert torch.equal(o, starts[i]), i
     b.fit(mb, srcs, dsts, sizes, init_ps=starts)
     rects = [(0, 0, w_, h_) for w_, h_ in sizes]
     outs = [torch.empty((h_, w_, 2), dtype=torch.float32, device="cuda") for w_, h_ in sizes]
