@@ -117,6 +117,11 @@ constexpr int field_waves(int rb) { return rb == 1 ? kFieldWaves : 2; }
 #ifndef EMDQ_EM_CHUNK
 #define EMDQ_EM_CHUNK 2
 #endif
+// single-pair EM: chunks end where the model's last fit stopped (1) or every
+// EMDQ_EM_CHUNK iterations (0)
+#ifndef EMDQ_EM_PREDICT
+#define EMDQ_EM_PREDICT 1
+#endif
 constexpr int kEmChunk = EMDQ_EM_CHUNK; // EM iterations enqueued between stop-flag reads
 #ifndef EMDQ_START_WGS
 #define EMDQ_START_WGS 2048   // batched learned start: workgroups over all pairs
@@ -3512,6 +3517,7 @@ struct emdq_model_s {
     DevState *em_st_dev = nullptr; // the same two slots, as the device addresses them
     hipEvent_t em_ev[2] = {};
     int em_seq = 0;                // sequence number of the last chunk enqueued
+    int em_stop_it = 0;            // the iteration whose kernels saw the last fit's stop (0: none)
     int em_slot_seq[2] = {};       // the number each slot will be published with
 };
 
@@ -3884,12 +3890,19 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
         // iterations are enqueued)
         const int seq = ++m->em_seq;
         m->em_slot_seq[k & 1] = seq;
-        for (int c = 0; c < kEmChunk && enqueued < prm.max_iter; ++c, ++enqueued) {
+        // chunks end where the model's last fit stopped, and run one
+        // iteration at a time after it: if this fit stops there too, one
+        // iteration instead of a whole chunk is enqueued past the stop
+        // (the results do not depend on the chunking)
+        int clen = kEmChunk;
+        if (EMDQ_EM_PREDICT && host_sync && m->em_stop_it > 0)
+            clen = enqueued < m->em_stop_it ? std::min(kEmChunk, m->em_stop_it - enqueued) : 1;
+        for (int c = 0; c < clen && enqueued < prm.max_iter; ++c, ++enqueued) {
             // EMDQ_PUBLISH_MSTEP: the state at the end of chunk k - 1 is
             // published by the first M-step of chunk k as it starts (its
             // write completes while that kernel runs); otherwise by the last
             // E-step / posterior kernel of chunk k as it ends
-            const bool last = c + 1 == kEmChunk || enqueued + 1 == prm.max_iter;
+            const bool last = c + 1 == clen || enqueued + 1 == prm.max_iter;
             DevState *slot =
                 last && host_sync && !EMDQ_PUBLISH_MSTEP ? &m->em_st_dev[k & 1] : nullptr;
             const int it = enqueued + 1;
@@ -3929,10 +3942,16 @@ emdq_status fit_impl(emdq_model m, const float *src_xy, const float *dst_xy, int
             const DevState &prev = m->em_st[ps];
             if (prev.done || prev.status < 0) {
                 stopped = true;
+                // fused: the E-step after the last iteration applies the
+                // stop rule; otherwise the last iteration's posterior kernel
+                m->em_stop_it = prev.status < 0 ? 0 : (fused ? prev.iter + 1 : prev.iter);
                 break;
             }
         }
-        if (enqueued >= prm.max_iter) break;
+        if (enqueued >= prm.max_iter) {
+            m->em_stop_it = 0;
+            break;
+        }
     }
     // once a stop flag was read, a fused fit is complete: the M-step before
     // the stopping E-step fitted with the final posteriors, and the
