@@ -451,3 +451,25 @@ def test_batch_with_failed_and_capped_pairs_matches_single_calls():
                 for key in ("p", "q", "scale", "mask"):
                     assert np.array_equal(rb[key], rs[key]), (max_iter, i, key)
         assert mb[0].status() == E.ENONFINITE
+
+
+def test_batched_start_small_and_ragged_pairs_equal_single_starts():
+    """Pairs with fewer than 16 other matches (zero features for the missing
+    neighbours), and sizes that leave a ragged last round: the batched
+    learned start (one match per lane) equals the single-pair start (one
+    match per wavefront) bit for bit."""
+    torch = torch_or_skip()
+    E = emdq()
+    base = synth.gen_config(2, 3, with_frame=False)
+    sizes_n = [2, 5, 16, 17, 33, 377, 1999]
+    w = E.load_start_weights()
+    srcs = [to_dev(base.src[:k], torch) for k in sizes_n]
+    dsts = [to_dev(base.dst[:k], torch) for k in sizes_n]
+    sizes = [(base.cfg.width, base.cfg.height)] * len(sizes_n)
+    outs = [torch.empty(k, dtype=torch.float32, device="cuda") for k in sizes_n]
+    b = E.Batch(len(sizes_n))
+    b.learned_start(srcs, dsts, sizes, w, outs)
+    for i, k in enumerate(sizes_n):
+        o = torch.empty(k, dtype=torch.float32, device="cuda")
+        E.emdq_learned_start(srcs[i], dsts[i], *sizes[i], w, o)
+        assert torch.equal(o, outs[i]), (i, k)
